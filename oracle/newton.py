@@ -1,0 +1,163 @@
+"""Oracle nonlinear solver: Newton's method with a direct sparse solve, the
+timestep loop and the material-balance report.
+
+Part of the CPU oracle (test infrastructure only; see the package docstring).
+
+Algorithm 1 (inexact Newton) with the forcing term fixed: the linear system
+J y = -R is solved by SuperLU (``linear='lu'``) or by the oracle's own
+decoupled CPR-FPF GMRES (``linear='cpr'``, relative tolerance ``eta``).
+
+Readings (the paper does not state them): the update chops the saturation
+change of each node to at most 0.2 per iteration and then clamps S_w to [0, 1];
+BHP-controlled wells have p_b pinned to the target after every update;
+convergence is the scaled max-norm test below; at most ``max_newton``
+iterations, then the step is cut in half (at most ``max_cuts`` times).  After a
+converged step a rate injector whose p_b exceeds its limit switches to BHP
+control at the limit and the step is repeated (at most once per step).
+"""
+import numpy as np
+import scipy.sparse.linalg as spla
+
+from . import physics as ph
+
+SAT_CHOP = 0.2
+
+
+def scaled_residual_norm(geo, R, dt, control):
+    """max over rows of |R| scaled to a dimensionless size.
+
+    Node rows: |R_a| dt / (rho_a,ref phi V) (a pore-volume fraction per step).
+    Rate rows: |R| / (rho_w,ref max(|Q|, 1e-6 m^3/s)).  BHP rows: |R| / target.
+    """
+    m = geo.m
+    n = geo.n
+    vphi = geo.vol * geo.phi
+    so = np.abs(R[0:4 * n:2]) * dt / (m["rho_o_ref"] * vphi)
+    sw = np.abs(R[1:4 * n:2]) * dt / (m["rho_w_ref"] * vphi)
+    worst = max(so.max(initial=0.0), sw.max(initial=0.0))
+    for w, wl in enumerate(m["wells"]):
+        r = abs(R[4 * n + 2 * w])
+        if control[w] == "rate":
+            worst = max(worst, r / (m["rho_w_ref"] * max(abs(wl["target"]), 1e-6)))
+        else:
+            target = wl["target"] if wl["control"] == "bhp" else wl["bhp_limit"]
+            worst = max(worst, r / max(abs(target), 1.0))
+    return worst
+
+
+def apply_update(geo, x, dx, control):
+    """x + dx with the saturation chop and clamp, and BHP pinning."""
+    n = geo.n
+    m = geo.m
+    y = x + dx
+    ds = np.clip(dx[1:4 * n:2], -SAT_CHOP, SAT_CHOP)
+    y[1:4 * n:2] = np.clip(x[1:4 * n:2] + ds, 0.0, 1.0)
+    for w, wl in enumerate(m["wells"]):
+        if control[w] != "rate":
+            y[4 * n + 2 * w] = wl["target"] if wl["control"] == "bhp" else wl["bhp_limit"]
+        y[4 * n + 2 * w + 1] = 0.0
+    return y
+
+
+def newton_solve(geo, x0, acc_old, dt, control, tol=1e-10, max_newton=20,
+                 linear="lu", eta=1e-10, cpr_opts=None):
+    """Newton iterations from x0.  Returns (x, converged, iterations, info)."""
+    x = x0.copy()
+    info = {"res": [], "lin_iters": []}
+    for it in range(max_newton + 1):
+        R = ph.residual(geo, x, acc_old, dt, control)
+        nrm = scaled_residual_norm(geo, R, dt, control)
+        info["res"].append(nrm)
+        if not np.isfinite(nrm):
+            return x, False, it, info
+        if nrm <= tol:
+            return x, True, it, info
+        if it == max_newton:
+            break
+        J = ph.jacobian(geo, x, dt, control)
+        if linear == "lu":
+            dx = spla.spsolve(J.tocsc(), -R)
+            info["lin_iters"].append(1)
+        else:
+            from . import cpr
+            dx, its, _ = cpr.solve(geo, J, -R, rtol=eta, **(cpr_opts or {}))
+            info["lin_iters"].append(its)
+        x = apply_update(geo, x, dx, control)
+    return x, False, max_newton, info
+
+
+def well_totals(geo, x, control):
+    """Total well mass rates (oil, water), positive into the reservoir."""
+    qo = qw = 0.0
+    for _, q_o, q_w in ph.well_rates(geo, x, control):
+        qo += float(np.sum(q_o))
+        qw += float(np.sum(q_w))
+    return qo, qw
+
+
+def _rel(err, mass):
+    return abs(err) / mass if mass > 0.0 else abs(err)
+
+
+def timestep(geo, x, dt, control, max_cuts=8, **newton_kw):
+    """Advance by dt (possibly in several cut sub-steps).
+
+    Returns (x_new, report) where report lists every accepted sub-step with its
+    material balance |M^{n+1} - M^n - dt Q(x^{n+1})| / M^{n+1} per phase."""
+    report = []
+    remaining = dt
+    cuts = 0
+    h = dt
+    control = list(control)
+    while remaining > 0.0:
+        h = min(h, remaining)
+        acc_old = ph.accumulation(geo, x)
+        switched = False
+        while True:
+            xn, ok, its, info = newton_solve(geo, x, acc_old, h, control, **newton_kw)
+            if not ok:
+                break
+            # BHP limit of rate injectors: switch once and redo
+            redo = False
+            if not switched:
+                _, _, bhp = ph.unpack_state(xn, geo.n)
+                for w, wl in enumerate(geo.m["wells"]):
+                    if control[w] == "rate" and wl["kind"] == "inj" and bhp[w] > wl["bhp_limit"]:
+                        control[w] = "bhp"
+                        redo = True
+            if redo:
+                switched = True
+                continue
+            break
+        if not ok:
+            cuts += 1
+            if cuts > max_cuts:
+                raise RuntimeError("timestep failed after %d cuts" % max_cuts)
+            h *= 0.5
+            continue
+        acc_new = ph.accumulation(geo, xn)
+        qo, qw = well_totals(geo, xn, control)
+        mo_old, mw_old = float(np.sum(acc_old[0])), float(np.sum(acc_old[1]))
+        mo_new, mw_new = float(np.sum(acc_new[0])), float(np.sum(acc_new[1]))
+        report.append(dict(dt=h, newton=its, lin_iters=info["lin_iters"],
+                           res=info["res"],
+                           mb_oil=_rel(mo_new - mo_old - h * qo, mo_new),
+                           mb_water=_rel(mw_new - mw_old - h * qw, mw_new),
+                           control=list(control)))
+        x = xn
+        remaining -= h
+    return x, report, control
+
+
+def run(model, steps=None, **kw):
+    """Run the model's schedule; returns (states after each step, reports)."""
+    geo = ph.Geometry(model)
+    x = ph.initial_state(model)
+    control = [w["control"] for w in model["wells"]]
+    states, reports = [], []
+    sched = model["schedule"] if steps is None else model["schedule"][:steps]
+    for dt in sched:
+        x, rep, control = timestep(geo, x, dt, control, **kw)
+        states.append(x.copy())
+        reports.append(rep)
+    return geo, states, reports

@@ -1,0 +1,258 @@
+"""Pins of the oracle's decoupling, block ILU(0), AMG, CPR-FPF and GMRES
+against textbook characterisations and closed forms (no GPU)."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import synth
+from oracle import cpr
+from oracle import physics as ph
+
+
+def _system(m, seed=3, dt=synth.DAY):
+    geo = ph.Geometry(m)
+    ctrl = [w["control"] for w in m["wells"]]
+    x = ph.pack_state(*synth.random_state(m, seed))
+    acc_old = ph.accumulation(geo, ph.initial_state(m))
+    R = ph.residual(geo, x, acc_old, dt, ctrl)
+    J = ph.jacobian(geo, x, dt, ctrl)
+    return geo, J, -R
+
+
+def test_decoupling_definition():
+    geo, J, b = _system(synth.config0())
+    indptr, indices, data = ph.to_bsr(geo, J)
+    dh, bh = cpr.decouple(2 * geo.n, indptr, indices, data, b)
+    Ah = ph.bsr_to_csr(indptr, indices, dh)
+    # the transformed system has the same solution
+    y = spla.spsolve(J.tocsc(), b)
+    yh = spla.spsolve(Ah.tocsc(), bh)
+    assert np.allclose(y, yh, rtol=1e-9, atol=0)
+    # the node's own saturation is removed from its first equation
+    nb = 2 * geo.n + geo.nw
+    rows = np.repeat(np.arange(nb), np.diff(indptr))
+    diag = indices == rows
+    node = rows < 2 * geo.n
+    a01 = np.abs(dh[diag & node][:, 0, 1])
+    scale = np.abs(data[diag & node][:, 0, 1]) + np.abs(data[diag & node][:, 1, 1])
+    assert np.all(a01 <= 1e-14 * scale)
+    # second rows untouched, well rows untouched
+    assert np.array_equal(dh[:, 1, :], data[:, 1, :])
+    assert np.array_equal(dh[rows >= 2 * geo.n], data[rows >= 2 * geo.n])
+
+
+def test_bilu0_textbook_characterisation():
+    """(L U)_ij = A_ij on every block (i, j) of the pattern."""
+    geo, J, b = _system(synth.model_tiny(4, 3, 2, seed=2))
+    indptr, indices, data = ph.to_bsr(geo, J)
+    dh, _ = cpr.decouple(2 * geo.n, indptr, indices, data, b)
+    perm = cpr.default_ordering(geo)
+    ilu = cpr.BlockILU0(indptr, indices, dh, perm)
+    nb = ilu.nb
+    Ld = {}
+    Ud = {}
+    for i, c, v in ilu.factors():
+        (Ld if c < i else Ud)[(i, c)] = v
+    for i in range(nb):
+        Ld[(i, i)] = np.eye(2)
+    # (LU)_ij = sum_k L_ik U_kj
+    pos = ilu.pos
+    Lrows = {}
+    for (i, k), v in Ld.items():
+        Lrows.setdefault(i, []).append((k, v))
+    for r in range(nb):
+        for t in range(indptr[r], indptr[r + 1]):
+            i, j = pos[r], pos[indices[t]]
+            acc = np.zeros((2, 2))
+            for k, lv in Lrows[i]:
+                if (k, j) in Ud:
+                    acc += lv @ Ud[(k, j)]
+            ref = dh[t]
+            assert np.allclose(acc, ref, rtol=1e-11, atol=1e-11 * np.abs(dh[indptr[r]:indptr[r + 1]]).max())
+
+
+def test_bilu0_exact_without_fill():
+    """With no wells and the ordering (m_c, f_c) cell by cell along a 1-D
+    chain, elimination creates no fill, so ILU(0) is the exact LU."""
+    m = synth.model_tiny(6, 1, 1, seed=4, wells=False)
+    geo, J, b = _system(m)
+    indptr, indices, data = ph.to_bsr(geo, J)
+    perm = np.ravel(np.column_stack([2 * np.arange(geo.n) + 1, 2 * np.arange(geo.n)]))
+    ilu = cpr.BlockILU0(indptr, indices, data, perm)
+    y = ilu.solve(b)
+    yref = spla.spsolve(J.tocsc(), b)
+    assert np.allclose(y, yref, rtol=1e-11, atol=0)
+
+
+def test_default_ordering_matrix_nodes_eliminated_exactly():
+    """Matrix nodes first: each couples only to its own fracture node, so their
+    elimination is exact and the fracture diagonal becomes the Schur complement."""
+    geo, J, b = _system(synth.config0())
+    indptr, indices, data = ph.to_bsr(geo, J)
+    perm = cpr.default_ordering(geo)
+    ilu = cpr.BlockILU0(indptr, indices, data, perm)
+    A = {}
+    nb = ilu.nb
+    for r in range(nb):
+        for t in range(indptr[r], indptr[r + 1]):
+            A[(r, indices[t])] = data[t]
+    red_f = perm[geo.n]          # first red fracture node (canonical index)
+    mm = red_f + 1
+    schur = A[(red_f, red_f)] - A[(red_f, mm)] @ np.linalg.inv(A[(mm, mm)]) @ A[(mm, red_f)]
+    i = ilu.pos[red_f]
+    assert np.allclose(np.linalg.inv(ilu.uinv[i]), schur, rtol=1e-12)
+
+
+def _poisson2d(nx, ny, shift=0.0, rng=None):
+    n = nx * ny
+    rows, cols, vals = [], [], []
+    for j in range(ny):
+        for i in range(nx):
+            c = i + nx * j
+            d = shift
+            for di, dj in ((1, 0), (-1, 0), (0, 1), (0, -1)):
+                ii, jj = i + di, j + dj
+                if 0 <= ii < nx and 0 <= jj < ny:
+                    w = 1.0 if rng is None else float(np.exp(rng.normal()))
+                    rows.append(c)
+                    cols.append(ii + nx * jj)
+                    vals.append(-w)
+                    d += w
+            rows.append(c)
+            cols.append(c)
+            vals.append(d)
+    A = sp.csr_matrix((vals, (rows, cols)), shape=(n, n))
+    # symmetrise weights for the random case
+    if rng is not None:
+        off = A - sp.diags(A.diagonal())
+        off = 0.5 * (off + off.T)
+        A = (off + sp.diags(-np.asarray(off.sum(axis=1)).ravel() + shift)).tocsr()
+    A.sort_indices()
+    return A
+
+
+def test_lowbias32_is_a_bijection_sample():
+    h = cpr.lowbias32(np.arange(1 << 20))
+    assert np.unique(h).shape[0] == 1 << 20
+    assert h.max() < 2 ** 32
+
+
+def test_pmis_independence_and_cover():
+    A = _poisson2d(20, 20, shift=0.01, rng=np.random.default_rng(1))
+    sm = cpr.strength(A, 0.25)
+    state = cpr.pmis(A, sm)
+    A = A.tocsr()
+    rows = np.repeat(np.arange(A.shape[0]), np.diff(A.indptr))
+    cols = A.indices
+    # no two C points are strongly connected
+    assert not np.any(sm & (state[rows] == 1) & (state[cols] == 1))
+    # every F point that influences someone depends strongly on a C point
+    nst = np.bincount(cols[sm], minlength=A.shape[0])
+    hasc = np.zeros(A.shape[0], dtype=bool)
+    hasc[rows[sm & (state[cols] == 1)]] = True
+    assert np.all(hasc[(state == -1) & (nst > 0)])
+
+
+def test_interpolation_1d_laplacian_is_linear():
+    """Tridiagonal Laplacian with alternate C points: interpolation is the
+    average of the two neighbours (1/2, 1/2)."""
+    n = 9
+    A = sp.diags([-np.ones(n - 1), 2 * np.ones(n), -np.ones(n - 1)], [-1, 0, 1]).tocsr()
+    sm = cpr.strength(A, 0.25)
+    state = np.where(np.arange(n) % 2 == 0, 1, -1)
+    P = cpr.interpolation(A, sm, state).toarray()
+    for i in range(1, n - 1, 2):
+        c = i // 2
+        assert P[i, c] == pytest.approx(0.5) and P[i, c + 1] == pytest.approx(0.5)
+        assert np.count_nonzero(P[i]) == 2
+
+
+def test_interpolation_reproduces_constants_on_zero_row_sums():
+    A = _poisson2d(16, 16, rng=np.random.default_rng(3))  # pure Neumann: zero row sums
+    sm = cpr.strength(A, 0.25)
+    state = cpr.pmis(A, sm)
+    P = cpr.interpolation(A, sm, state)
+    rs = np.asarray(P.sum(axis=1)).ravel()
+    has = np.diff(P.tocsr().indptr) > 0
+    assert np.allclose(rs[has], 1.0, rtol=1e-12)
+    assert np.max(np.diff(P.tocsr().indptr)) <= 4
+
+
+def test_amg_galerkin_and_exact_coarse():
+    geo, J, b = _system(synth.config0())
+    indptr, indices, data = ph.to_bsr(geo, J)
+    dh, _ = cpr.decouple(2 * geo.n, indptr, indices, data, b)
+    Ap = cpr.pressure_matrix(indptr, indices, dh)
+    amg = cpr.AMG(Ap, max_coarse=40)
+    assert len(amg.levels) >= 3
+    for l in range(len(amg.levels) - 1):
+        lv = amg.levels[l]
+        Ac = amg.levels[l + 1]["A"].toarray()
+        ref = lv["P"].toarray().T @ lv["A"].toarray() @ lv["P"].toarray()
+        assert np.allclose(Ac, ref, rtol=1e-10, atol=1e-12 * np.abs(ref).max())
+    # one-level hierarchy: the V-cycle is an exact solve
+    one = cpr.AMG(Ap, max_coarse=10 ** 6)
+    assert len(one.levels) == 1
+    rhs = np.random.default_rng(0).standard_normal(Ap.shape[0])
+    x = one.vcycle(rhs)
+    assert np.allclose(Ap @ x, rhs, rtol=1e-9, atol=1e-9 * np.abs(rhs).max())
+
+
+def test_vcycle_contracts_on_poisson():
+    A = _poisson2d(40, 40, shift=1e-3, rng=np.random.default_rng(2))
+    amg = cpr.AMG(A, max_coarse=50)
+    assert len(amg.levels) >= 3
+    rng = np.random.default_rng(5)
+    xs = rng.standard_normal(A.shape[0])
+    b = A @ xs
+    x = np.zeros_like(b)
+    e0 = np.linalg.norm(xs)
+    for _ in range(8):
+        x = x + amg.vcycle(b - A @ x)
+    # l1-Jacobi V(1,1): a contraction of about 0.6 per cycle here
+    assert np.linalg.norm(xs - x) <= 0.7 ** 8 * e0
+
+
+def test_gmres_arnoldi_relation_and_orthogonality():
+    A = _poisson2d(15, 15, shift=0.1, rng=np.random.default_rng(4)) + sp.diags(np.linspace(0, 1, 225))
+    A = A.tocsr()
+    b = np.random.default_rng(1).standard_normal(225)
+    Dinv = 1.0 / A.diagonal()
+    tr = {}
+    x, its, rel = cpr.gmres(lambda v: A @ v, lambda v: Dinv * v, b, 1e-14, restart=20, maxit=20, trace=tr)
+    V, Z, H = tr["V"], tr["Z"], tr["H"]
+    k = Z.shape[0]
+    AZ = np.stack([A @ Z[j] for j in range(k)])
+    lhs = AZ.T
+    rhs = V.T @ H
+    assert np.linalg.norm(lhs - rhs) <= 1e-12 * spla.norm(A) * np.sqrt(k)
+    assert np.abs(V @ V.T - np.eye(V.shape[0])).max() <= 1e-12
+
+
+def test_gmres_finite_termination_diagonal():
+    k = 7
+    d = np.repeat(np.arange(1.0, k + 1.0), 20)
+    A = sp.diags(d).tocsr()
+    b = np.random.default_rng(2).standard_normal(d.shape[0])
+    x, its, rel = cpr.gmres(lambda v: A @ v, lambda v: v, b, 1e-12, restart=30)
+    assert its <= k
+    assert rel <= 1e-12
+
+
+def test_cpr_with_exact_full_stage_converges_in_one_iteration():
+    geo, J, b = _system(synth.config0())
+    y, its, rel = cpr.solve(geo, J, b, rtol=1e-10, exact_f=True)
+    assert its == 1
+
+
+def test_cpr_gmres_matches_direct_solve():
+    geo, J, b = _system(synth.config0(), seed=11)
+    y, its, rel = cpr.solve(geo, J, b, rtol=1e-12)
+    yref = spla.spsolve(J.tocsc(), b)
+    assert rel <= 1e-12
+    # compare the two components on their own scales
+    for comp in (0, 1):
+        a, r = y[comp:4 * geo.n:2], yref[comp:4 * geo.n:2]
+        assert np.abs(a - r).max() <= 1e-8 * np.abs(r).max()
+    assert 1 <= its <= 30
