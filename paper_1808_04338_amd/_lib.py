@@ -1,0 +1,131 @@
+"""ctypes view of the dpsim C ABI (include/dpsim.h).
+
+Argument marshalling only: every computation happens in libdpsim.so.  Loading
+fails loudly when the library has not been built.
+"""
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdpsim.so")
+
+DP_OK = 0
+DP_E_INVALID = -1
+DP_E_NOMEM = -2
+DP_E_DEVICE = -3
+DP_E_NOCONV = -4
+DP_E_STATE = -5
+DP_E_NUMERIC = -6
+STATUS_NAMES = {0: "DP_OK", -1: "DP_E_INVALID", -2: "DP_E_NOMEM", -3: "DP_E_DEVICE",
+                -4: "DP_E_NOCONV", -5: "DP_E_STATE", -6: "DP_E_NUMERIC"}
+
+DP_WELL_INJ, DP_WELL_PROD = 0, 1
+DP_CTRL_RATE, DP_CTRL_BHP = 0, 1
+DP_FP64, DP_FP32 = 0, 1
+
+_dptr = C.POINTER(C.c_double)
+_iptr = C.POINTER(C.c_int32)
+_lptr = C.POINTER(C.c_int64)
+
+
+class DpWell(C.Structure):
+    _fields_ = [("i", C.c_int32), ("j", C.c_int32), ("k0", C.c_int32), ("k1", C.c_int32),
+                ("kind", C.c_int32), ("control", C.c_int32),
+                ("target", C.c_double), ("bhp_limit", C.c_double),
+                ("rw", C.c_double), ("skin", C.c_double)]
+
+
+class DpSimDesc(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
+                ("top_depth", C.c_double), ("gravity", C.c_double),
+                ("kx", _dptr), ("ky", _dptr), ("kz", _dptr), ("km", _dptr),
+                ("phi_f", _dptr), ("phi_m", _dptr),
+                ("sigma", C.c_double),
+                ("rho_w_ref", C.c_double), ("rho_o_ref", C.c_double), ("p_ref", C.c_double),
+                ("c_w", C.c_double), ("c_o", C.c_double),
+                ("mu_w", C.c_double), ("mu_o", C.c_double),
+                ("swc", C.c_double), ("sor", C.c_double), ("n_w", C.c_double), ("n_o", C.c_double),
+                ("krw_max", C.c_double), ("kro_max", C.c_double),
+                ("nwells", C.c_int32), ("wells", C.POINTER(DpWell)),
+                ("precond_precision", C.c_int32), ("gmres_restart", C.c_int32),
+                ("lin_maxit", C.c_int32), ("lin_rtol", C.c_double),
+                ("amg_coarse_max", C.c_int32), ("amg_max_levels", C.c_int32),
+                ("amg_theta", C.c_double), ("amg_trunc", C.c_int32),
+                ("newton_tol", C.c_double), ("max_newton", C.c_int32), ("max_cuts", C.c_int32)]
+
+
+class DpNewtonInfo(C.Structure):
+    _fields_ = [("converged", C.c_int32), ("lin_iters", C.c_int32),
+                ("res_scaled", C.c_double), ("lin_rel_res", C.c_double)]
+
+
+class DpStepInfo(C.Structure):
+    _fields_ = [("dt", C.c_double), ("substeps", C.c_int32), ("cuts", C.c_int32),
+                ("newton_iters", C.c_int32), ("lin_iters", C.c_int32),
+                ("mb_oil", C.c_double), ("mb_water", C.c_double), ("res_scaled", C.c_double)]
+
+
+_SIGS = {
+    "sim_footprint": [C.POINTER(DpSimDesc), C.POINTER(C.c_size_t)],
+    "sim_create": [C.POINTER(DpSimDesc), _dptr, _dptr, C.c_void_p, C.c_size_t, C.c_void_p,
+                   C.POINTER(C.c_void_p)],
+    "sim_destroy": [C.c_void_p],
+    "sim_mark_old": [C.c_void_p],
+    "assemble_residual_jacobian": [C.c_void_p, C.c_double, _dptr],
+    "cpr_fpf_setup": [C.c_void_p],
+    "krylov_solve": [C.c_void_p, C.c_double, C.c_int32, _iptr, _dptr],
+    "newton_update": [C.c_void_p],
+    "newton_step": [C.c_void_p, C.c_double, C.c_double, C.POINTER(DpNewtonInfo)],
+    "timestep": [C.c_void_p, C.c_double, C.POINTER(DpStepInfo)],
+    "batch_timestep": [C.POINTER(C.c_void_p), C.c_int32, _dptr, C.POINTER(DpStepInfo), _iptr],
+    "sim_get_state": [C.c_void_p, _dptr, _dptr, _dptr],
+    "sim_set_state": [C.c_void_p, _dptr, _dptr, _dptr],
+    "sim_system_size": [C.c_void_p, _iptr, _lptr],
+    "sim_export_system": [C.c_void_p, C.c_int32, _iptr, _iptr, _dptr, _dptr],
+    "sim_export_ilu": [C.c_void_p, _iptr, _iptr, _iptr, _dptr],
+    "sim_amg_info": [C.c_void_p, _iptr, _iptr, _lptr],
+    "sim_export_amg_level": [C.c_void_p, C.c_int32, _iptr, _iptr, _iptr, _dptr, _iptr, _iptr, _dptr,
+                             _lptr],
+    "sim_apply_precond": [C.c_void_p, _dptr, _dptr],
+    "sim_apply_matrix": [C.c_void_p, _dptr, _dptr],
+    "sim_apply_stage": [C.c_void_p, C.c_int32, _dptr, _dptr],
+    "dp_selftest_dense_inverse": [_dptr, C.c_int32, _dptr, C.c_void_p, C.c_size_t, C.c_void_p],
+    "sim_enable_timing": [C.c_void_p, C.c_int32],
+    "sim_phase_time": [C.c_void_p, C.c_int32, _dptr, _lptr],
+}
+
+_lib = None
+
+
+def load():
+    """Load libdpsim.so (built by paper_1808_04338_amd.build).  Raises if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libdpsim.so is not built (run __graft_entry__.build()); "
+                           "there is no fallback implementation")
+    lib = C.CDLL(LIB_PATH)
+    for name, args in _SIGS.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = C.c_int32
+    lib.sim_last_error.argtypes = [C.c_void_p]
+    lib.sim_last_error.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+class DpError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(code, str(code)), msg))
+        self.code = code
+
+
+def check(code, handle=None):
+    if code != DP_OK:
+        lib = load()
+        msg = lib.sim_last_error(handle)
+        raise DpError(code, msg.decode() if msg else "")
+    return code

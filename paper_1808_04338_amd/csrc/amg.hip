@@ -1,0 +1,1017 @@
+// Classical algebraic multigrid on the pressure system: setup (strength of
+// connection, PMIS splitting, distance-two interpolation in matrix-product form
+// with truncation, Galerkin coarse operators) and the V(1,1) cycle with
+// l1-Jacobi smoothing.  The coarsest operator is inverted densely by a blocked
+// Gauss-Jordan whose rank-32 updates run on FP64 MFMA.
+//
+// Setup runs in FP64; the apply copies (SELL-64 operators, l1 diagonals, dense
+// coarse inverse) are kept in the preconditioner precision.
+#include <cstdlib>
+#include <vector>
+
+#include "kernels.h"
+#include "primitives.h"
+
+namespace dp {
+
+constexpr int C_BASE = 1 << 20;  // PMIS state >= C_BASE: C point chosen in iteration state-C_BASE
+constexpr int ST_U = 0;
+constexpr int ST_F = -1;
+
+// ---------------------------------------------------------------------------
+// Level-0 pressure matrix: entry (0,0) of each block of the decoupled matrix
+// ---------------------------------------------------------------------------
+__global__ void extract_ap_kernel(BMat<double> A, const int* __restrict__ rowptr,
+                                  const int* __restrict__ src, const int* __restrict__ fperf, int n,
+                                  int nb, double* val) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nb) return;
+    for (int e = rowptr[r]; e < rowptr[r + 1]; ++e) {
+        int code = src[e];
+        double v;
+        if (r < n) {
+            v = code == 0 ? A.d0[r].x : A.m0[r].x;
+        } else if (r < 2 * n) {
+            int q = r - n;
+            if (code < 7) v = A.f0[(int64_t)code * n + q].x;
+            else if (code == 7) v = A.d0[r].x;
+            else v = A.fw0[fperf[q]].x;
+        } else {
+            v = code < 0 ? A.d0[r].x : A.wf0[code].x;
+        }
+        val[e] = v;
+    }
+}
+
+void amg_extract_level0(dp_sim* s) {
+    Topo& t = s->topo;
+    extract_ap_kernel<<<ceil_div(t.nb, 256), 256, 0, s->stream>>>(s->A, s->Ap0.rowptr, s->ap_src,
+                                                                 t.fperf, t.n, t.nb, s->Ap0.val);
+    DP_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// Strength: j strongly influences i if -a_ij sgn(a_ii) >= theta max_k(-a_ik sgn(a_ii))
+// and that maximum is > 0.  Also |S^T_i| (integer atomics) and the diagonal.
+// ---------------------------------------------------------------------------
+__global__ void strength_kernel(Csr A, double theta, unsigned char* smask, int* nst, double* diag) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    int b = A.rowptr[i], e1 = A.rowptr[i + 1];
+    double d = 0.0;
+    for (int e = b; e < e1; ++e)
+        if (A.col[e] == i) d = A.val[e];
+    diag[i] = d;
+    double sg = d < 0.0 ? -1.0 : 1.0;
+    double mx = -INFINITY;
+    for (int e = b; e < e1; ++e)
+        if (A.col[e] != i) mx = fmax(mx, -A.val[e] * sg);
+    for (int e = b; e < e1; ++e) {
+        int j = A.col[e];
+        bool st = (j != i) && (mx > 0.0) && (-A.val[e] * sg >= theta * mx);
+        smask[e] = st ? 1 : 0;
+        if (st) atomicAdd(&nst[j], 1);
+    }
+}
+
+// lowbias32 integer hash (C. Wellons)
+__device__ inline uint32_t lowbias32(uint32_t x) {
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+
+__global__ void pmis_init(int n, const int* __restrict__ nst, int* state, double* wgt) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    state[i] = nst[i] == 0 ? ST_F : ST_U;
+    wgt[i] = (double)nst[i] + (double)lowbias32((uint32_t)i) * (1.0 / 4294967296.0);
+}
+
+// For every strong edge with both ends undecided, the end with the smaller
+// (weight, index) is beaten in this iteration.
+__global__ void pmis_beat(Csr A, const unsigned char* __restrict__ smask, const int* __restrict__ state,
+                          const double* __restrict__ wgt, int iter, int* beaten) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n || state[i] != ST_U) return;
+    double wi = wgt[i];
+    for (int e = A.rowptr[i]; e < A.rowptr[i + 1]; ++e) {
+        if (!smask[e]) continue;
+        int j = A.col[e];
+        if (state[j] != ST_U) continue;
+        double wj = wgt[j];
+        bool j_wins = (wj > wi) || (wj == wi && j > i);
+        if (j_wins) beaten[i] = iter;
+        else beaten[j] = iter;
+    }
+}
+
+__global__ void pmis_select(int n, int* state, const int* __restrict__ beaten, int iter) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || state[i] != ST_U) return;
+    if (beaten[i] != iter) state[i] = C_BASE + iter;
+}
+
+// Undecided points that depend strongly on a C point of this iteration become F.
+__global__ void pmis_fpass(Csr A, const unsigned char* __restrict__ smask, int* state, int iter,
+                           int* undecided) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n || state[i] != ST_U) return;
+    bool f = false;
+    for (int e = A.rowptr[i]; e < A.rowptr[i + 1]; ++e)
+        if (smask[e] && state[A.col[e]] == C_BASE + iter) f = true;
+    if (f) state[i] = ST_F;
+    else atomicAdd(undecided, 1);
+}
+
+__global__ void pmis_final(int n, const int* __restrict__ state, int* cf, int64_t* cflag) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    bool c = state[i] >= C_BASE;
+    cf[i] = c ? 1 : -1;
+    cflag[i] = c ? 1 : 0;
+}
+
+// ---------------------------------------------------------------------------
+// Interpolation (distance two, matrix-product form):
+//   abar_kj = a_kj if j strong C of k and a_kj a_kk < 0;  beta_k = sum_j abar_kj
+//   d_i = a_ii + sum_{weak n} a_in + sum_{k strong F, beta_k = 0} a_ik
+//   s_ij = a_ij [j strong C] + sum_{k strong F, beta_k != 0} a_ik (abar_kj / beta_k)
+//   w_ij = -s_ij / d_i, truncated to the largest entries (row sum kept)
+// ---------------------------------------------------------------------------
+__global__ void interp_beta(Csr A, const unsigned char* __restrict__ smask, const int* __restrict__ cf,
+                            const double* __restrict__ diag, double* beta, int* g) {
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= A.n) return;
+    double bsum = 0.0;
+    int cnt = 0;
+    if (cf[k] < 0) {
+        double dk = diag[k];
+        for (int e = A.rowptr[k]; e < A.rowptr[k + 1]; ++e) {
+            int j = A.col[e];
+            double v = A.val[e];
+            if (smask[e] && cf[j] > 0 && v * dk < 0.0) {
+                bsum += v;
+                ++cnt;
+            }
+        }
+    }
+    beta[k] = bsum;
+    g[k] = cnt;
+}
+
+__global__ void interp_count(Csr A, const unsigned char* __restrict__ smask, const int* __restrict__ cf,
+                             const double* __restrict__ diag, const double* __restrict__ beta,
+                             const int* __restrict__ g, double* dd, int64_t* cnt) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    int64_t c = 0;
+    double d = diag[i];
+    if (cf[i] < 0) {
+        int b = A.rowptr[i], e1 = A.rowptr[i + 1];
+        for (int e = b; e < e1; ++e) {
+            int j = A.col[e];
+            if (j == i) continue;
+            if (!smask[e]) d += A.val[e];
+        }
+        for (int e = b; e < e1; ++e) {
+            int j = A.col[e];
+            if (j == i || !smask[e]) continue;
+            if (cf[j] > 0) {
+                ++c;
+            } else if (beta[j] != 0.0) {
+                c += g[j];
+            } else {
+                d += A.val[e];
+            }
+        }
+    }
+    dd[i] = d;
+    cnt[i] = c;
+}
+
+__global__ void interp_expand(Csr A, const unsigned char* __restrict__ smask, const int* __restrict__ cf,
+                              const int64_t* __restrict__ cidx, const double* __restrict__ diag,
+                              const double* __restrict__ beta, const int64_t* __restrict__ off, int cbits,
+                              uint64_t* keys, double* vals) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n || cf[i] > 0) return;
+    int64_t o = off[i];
+    uint64_t rk = (uint64_t)i << cbits;
+    for (int e = A.rowptr[i]; e < A.rowptr[i + 1]; ++e) {
+        int j = A.col[e];
+        if (j == i || !smask[e]) continue;
+        double a = A.val[e];
+        if (cf[j] > 0) {
+            keys[o] = rk | (uint64_t)cidx[j];
+            vals[o] = a;
+            ++o;
+        } else if (beta[j] != 0.0) {
+            double bk = beta[j], dk = diag[j];
+            for (int f = A.rowptr[j]; f < A.rowptr[j + 1]; ++f) {
+                int jj = A.col[f];
+                double v = A.val[f];
+                if (smask[f] && cf[jj] > 0 && v * dk < 0.0) {
+                    keys[o] = rk | (uint64_t)cidx[jj];
+                    vals[o] = a * (v / bk);
+                    ++o;
+                }
+            }
+        }
+    }
+}
+
+constexpr int TRUNC_MAX = 8;
+
+// Selection of the kept entries of one F row: the 'trunc' largest |w|
+// (ties: lower column), in that order.
+struct Sel {
+    int n;
+    int col[TRUNC_MAX];
+    double w[TRUNC_MAX];
+};
+
+__device__ inline bool better(double aw, int ac, double bw, int bc) {
+    double fa = fabs(aw), fb = fabs(bw);
+    return fa > fb || (fa == fb && ac < bc);
+}
+
+__device__ inline void select_row(const Csr& W, int i, double d, int trunc, Sel& sel, double& total,
+                                  int& nnzw) {
+    sel.n = 0;
+    total = 0.0;
+    nnzw = 0;
+    for (int e = W.rowptr[i]; e < W.rowptr[i + 1]; ++e) {
+        double w = -W.val[e] / d;
+        if (w == 0.0) continue;
+        ++nnzw;
+        total += w;
+        int c = W.col[e];
+        // insertion into the sorted selection
+        int pos = sel.n;
+        while (pos > 0 && better(w, c, sel.w[pos - 1], sel.col[pos - 1])) --pos;
+        if (pos < trunc) {
+            int last = sel.n < trunc ? sel.n : trunc - 1;
+            for (int t = last; t > pos; --t) {
+                sel.w[t] = sel.w[t - 1];
+                sel.col[t] = sel.col[t - 1];
+            }
+            sel.w[pos] = w;
+            sel.col[pos] = c;
+            if (sel.n < trunc) ++sel.n;
+        }
+    }
+}
+
+__global__ void pcount_kernel(Csr W, const int* __restrict__ cf, const double* __restrict__ dd, int trunc,
+                              int64_t* cnt) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= W.n) return;
+    if (cf[i] > 0) {
+        cnt[i] = 1;
+        return;
+    }
+    double d = dd[i];
+    if (d == 0.0) {
+        cnt[i] = 0;
+        return;
+    }
+    int nz = 0;
+    for (int e = W.rowptr[i]; e < W.rowptr[i + 1]; ++e)
+        if (-W.val[e] / d != 0.0) ++nz;
+    cnt[i] = nz < trunc ? nz : trunc;
+}
+
+__global__ void pfill_kernel(Csr W, const int* __restrict__ cf, const int64_t* __restrict__ cidx,
+                             const double* __restrict__ dd, int trunc, const int64_t* __restrict__ off,
+                             int* pcol, double* pval) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= W.n) return;
+    int64_t o = off[i];
+    if (cf[i] > 0) {
+        pcol[o] = (int)cidx[i];
+        pval[o] = 1.0;
+        return;
+    }
+    double d = dd[i];
+    if (d == 0.0) return;
+    Sel sel;
+    double total;
+    int nnzw;
+    select_row(W, i, d, trunc, sel, total, nnzw);
+    double scale = 1.0;
+    if (nnzw > trunc) {
+        double kept = 0.0;
+        for (int t = 0; t < sel.n; ++t) kept += sel.w[t];
+        scale = kept != 0.0 ? total / kept : 1.0;
+    }
+    // kept entries in column order
+    for (int a = 1; a < sel.n; ++a)
+        for (int b = a; b > 0 && sel.col[b] < sel.col[b - 1]; --b) {
+            int tc = sel.col[b];
+            sel.col[b] = sel.col[b - 1];
+            sel.col[b - 1] = tc;
+            double tw = sel.w[b];
+            sel.w[b] = sel.w[b - 1];
+            sel.w[b - 1] = tw;
+        }
+    for (int t = 0; t < sel.n; ++t) {
+        pcol[o + t] = sel.col[t];
+        pval[o + t] = nnzw > trunc ? sel.w[t] * scale : sel.w[t];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Transpose and Galerkin product by expansion + stable sort + ordered sums
+// ---------------------------------------------------------------------------
+__global__ void transpose_expand(Csr P, int rbits, uint64_t* keys, double* vals) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= P.n) return;
+    for (int e = P.rowptr[i]; e < P.rowptr[i + 1]; ++e) {
+        keys[e] = ((uint64_t)P.col[e] << rbits) | (uint64_t)i;
+        vals[e] = P.val[e];
+    }
+}
+
+__global__ void rap_count(Csr A, Csr P, int64_t* cnt) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    int64_t pi = P.rowptr[i + 1] - P.rowptr[i];
+    int64_t s = 0;
+    for (int e = A.rowptr[i]; e < A.rowptr[i + 1]; ++e) {
+        int k = A.col[e];
+        s += P.rowptr[k + 1] - P.rowptr[k];
+    }
+    cnt[i] = pi * s;
+}
+
+// A_c(I,J) = sum_{i,k} P_iI a_ik P_kJ
+__global__ void rap_expand(Csr A, Csr P, const int64_t* __restrict__ off, int cbits, uint64_t* keys,
+                           double* vals) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    int64_t o = off[i];
+    int pb = P.rowptr[i], pe = P.rowptr[i + 1];
+    if (pb == pe) return;
+    for (int e = A.rowptr[i]; e < A.rowptr[i + 1]; ++e) {
+        int k = A.col[e];
+        double a = A.val[e];
+        int qb = P.rowptr[k], qe = P.rowptr[k + 1];
+        for (int u = pb; u < pe; ++u) {
+            uint64_t rk = (uint64_t)P.col[u] << cbits;
+            double pa = P.val[u] * a;
+            for (int v = qb; v < qe; ++v) {
+                keys[o] = rk | (uint64_t)P.col[v];
+                vals[o] = pa * P.val[v];
+                ++o;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// SELL-64 conversion and the l1-Jacobi diagonal
+// ---------------------------------------------------------------------------
+__global__ void sell_width(Csr A, int nslices, int64_t* w) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= nslices) return;
+    int mx = 0;
+    for (int r = s * 64; r < s * 64 + 64 && r < A.n; ++r) mx = max(mx, A.rowptr[r + 1] - A.rowptr[r]);
+    w[s] = (int64_t)mx * 64;
+}
+
+__global__ void sell_ptr(const int64_t* __restrict__ off, int nslices, int64_t total, int* sptr) {
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s > nslices) return;
+    sptr[s] = s < nslices ? (int)off[s] : (int)total;
+}
+
+template <class T>
+__global__ void sell_fill(Csr A, const int* __restrict__ sptr, int pad_self, int* col, T* val) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    int s = r / 64, lane = r % 64;
+    if (s >= (A.n + 63) / 64) return;
+    int base = sptr[s];
+    int w = (sptr[s + 1] - base) / 64;
+    int b = 0, len = 0;
+    if (r < A.n) {
+        b = A.rowptr[r];
+        len = A.rowptr[r + 1] - b;
+    }
+    for (int k = 0; k < w; ++k) {
+        int e = base + k * 64 + lane;
+        if (k < len) {
+            col[e] = A.col[b + k];
+            val[e] = (T)A.val[b + k];
+        } else {
+            col[e] = (pad_self && r < A.n) ? r : 0;
+            val[e] = (T)0;
+        }
+    }
+}
+
+template <class T>
+__global__ void l1_kernel(Csr A, T* dinv) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
+    double d = 0.0, s = 0.0;
+    for (int e = A.rowptr[i]; e < A.rowptr[i + 1]; ++e) {
+        if (A.col[e] == i) d = A.val[e];
+    }
+    for (int e = A.rowptr[i]; e < A.rowptr[i + 1]; ++e)
+        if (A.col[e] != i) s += fabs(A.val[e]);
+    double sg = d < 0.0 ? -1.0 : 1.0;
+    dinv[i] = (T)(1.0 / (d + sg * s));
+}
+
+__global__ void i64_to_i32(const int64_t* __restrict__ a, int n, int64_t total, int* b) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > n) return;
+    b[i] = i < n ? (int)a[i] : (int)total;
+}
+
+// ---------------------------------------------------------------------------
+// Dense coarse inverse: blocked Gauss-Jordan, 32-wide panels.  The diagonal
+// panel block is inverted with partial pivoting inside the block; the rank-32
+// updates of the rest of the matrix use V_MFMA_F64_16X16X4_F64.
+// ---------------------------------------------------------------------------
+constexpr int GJ_B = 32;
+typedef double d4v __attribute__((ext_vector_type(4)));
+
+__global__ void dense_fill(Csr A, int np, double* M) {
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)np * np) return;
+    int r = (int)(idx / np), c = (int)(idx % np);
+    double v = (r == c && r >= A.n) ? 1.0 : 0.0;
+    if (r < A.n && c < A.n) {
+        for (int e = A.rowptr[r]; e < A.rowptr[r + 1]; ++e)
+            if (A.col[e] == c) v = A.val[e];
+    }
+    M[idx] = v;
+}
+
+// Invert the 32x32 block M_kk into P (row-major 32x32) with partial pivoting.
+__global__ void __launch_bounds__(256) gj_diag(const double* __restrict__ M, int np, int kb, double* P,
+                                               int* bad) {
+    __shared__ double a[GJ_B][2 * GJ_B + 1];
+    __shared__ double mult[GJ_B];
+    __shared__ int piv;
+    int t = threadIdx.x;
+    int k0 = kb * GJ_B;
+    for (int i = t; i < GJ_B * 2 * GJ_B; i += 256) {
+        int r = i / (2 * GJ_B), c = i % (2 * GJ_B);
+        a[r][c] = c < GJ_B ? M[(int64_t)(k0 + r) * np + k0 + c] : (c - GJ_B == r ? 1.0 : 0.0);
+    }
+    __syncthreads();
+    for (int c = 0; c < GJ_B; ++c) {
+        if (t == 0) {
+            int p = c;
+            double best = fabs(a[c][c]);
+            for (int r = c + 1; r < GJ_B; ++r)
+                if (fabs(a[r][c]) > best) {
+                    best = fabs(a[r][c]);
+                    p = r;
+                }
+            piv = p;
+            if (best == 0.0) *bad = 1;
+        }
+        __syncthreads();
+        int p = piv;
+        if (p != c && t < 2 * GJ_B) {
+            double tmp = a[c][t];
+            a[c][t] = a[p][t];
+            a[p][t] = tmp;
+        }
+        __syncthreads();
+        double inv = 1.0 / a[c][c];
+        __syncthreads();
+        if (t < 2 * GJ_B) a[c][t] *= inv;
+        __syncthreads();
+        // elimination needs the multipliers of column c before any update
+        if (t < GJ_B) mult[t] = a[t][c];
+        __syncthreads();
+        for (int i = t; i < GJ_B * 2 * GJ_B; i += 256) {
+            int r = i / (2 * GJ_B), cc = i % (2 * GJ_B);
+            if (r != c) a[r][cc] -= mult[r] * a[c][cc];
+        }
+        __syncthreads();
+    }
+    for (int i = t; i < GJ_B * GJ_B; i += 256) {
+        int r = i / GJ_B, c = i % GJ_B;
+        P[i] = a[r][GJ_B + c];
+    }
+}
+
+// Output element i of lane l of a 16x16 FP64 MFMA tile (A row r supplied by
+// lane r + 16k): row (l/16) + 4i, column l%16 (checked on the device).
+__device__ inline void tile_rc(int i, int qr, int qc, int& r, int& c) {
+    int lane = threadIdx.x % WAVE;
+    r = qr * 16 + (lane / 16) + 4 * i;
+    c = qc * 16 + lane % 16;
+}
+
+// 32x32 tile product acc = X (32x32, leading dim ldx) * Y (32x32, ldy) with
+// MFMA: wave q of 4 computes the 16x16 quadrant (q/2, q%2).
+__device__ inline d4v mfma_tile(const double* X, int64_t ldx, const double* Y, int64_t ldy, int qr,
+                                int qc) {
+    int lane = threadIdx.x % WAVE;
+    d4v acc = {0.0, 0.0, 0.0, 0.0};
+    int ar = qr * 16 + lane % 16;
+    int bc = qc * 16 + lane % 16;
+    int kk = lane / 16;
+#pragma unroll
+    for (int t = 0; t < GJ_B / 4; ++t) {
+        double av = X[(int64_t)ar * ldx + 4 * t + kk];
+        double bv = Y[(int64_t)(4 * t + kk) * ldy + bc];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+// The same 32x32 tile product with plain FMAs and the MFMA output layout
+// (reference path, selected with DPSIM_GJ_PLAIN=1).
+__device__ inline d4v fma_tile(const double* X, int64_t ldx, const double* Y, int64_t ldy, int qr,
+                               int qc) {
+    d4v acc = {0.0, 0.0, 0.0, 0.0};
+    for (int i = 0; i < 4; ++i) {
+        int r, c;
+        tile_rc(i, qr, qc, r, c);
+        double s = 0.0;
+        for (int k = 0; k < GJ_B; ++k) s += X[(int64_t)r * ldx + k] * Y[(int64_t)k * ldy + c];
+        acc[i] = s;
+    }
+    return acc;
+}
+
+template <bool MF>
+__device__ inline d4v tile_mm(const double* X, int64_t ldx, const double* Y, int64_t ldy, int qr, int qc) {
+    return MF ? mfma_tile(X, ldx, Y, ldy, qr, qc) : fma_tile(X, ldx, Y, ldy, qr, qc);
+}
+
+
+
+// Row panel k: M_kj <- P M_kj (j != k).  Also copies the old column panel
+// M_ik into Cbuf (np x 32).
+template <bool MF>
+__global__ void __launch_bounds__(256) gj_row(double* M, int np, int kb, const double* __restrict__ P,
+                                              double* Cbuf) {
+    int nbk = np / GJ_B;
+    int tile = blockIdx.x;
+    int wv = threadIdx.x / WAVE;
+    int qr = wv / 2, qc = wv % 2;
+    if (tile < nbk) {
+        int jb = tile;
+        if (jb == kb) return;
+        double* Y = M + (int64_t)kb * GJ_B * np + jb * GJ_B;
+        d4v acc = tile_mm<MF>(P, GJ_B, Y, np, qr, qc);
+        __syncthreads();  // every wave has read its operands of Y before any write
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            int r, c;
+            tile_rc(i, qr, qc, r, c);
+            Y[(int64_t)r * np + c] = acc[i];
+        }
+    } else {
+        int ib = tile - nbk;
+        for (int e = threadIdx.x; e < GJ_B * GJ_B; e += 256) {
+            int r = e / GJ_B, c = e % GJ_B;
+            Cbuf[(int64_t)(ib * GJ_B + r) * GJ_B + c] = M[(int64_t)(ib * GJ_B + r) * np + kb * GJ_B + c];
+        }
+    }
+}
+
+// All tiles (i, j) with i != k: M_ij -= C_i M_kj (j != k), M_ik = -C_i P.
+// Tile (k, k) becomes P.
+template <bool MF>
+__global__ void __launch_bounds__(256) gj_update(double* M, int np, int kb, const double* __restrict__ P,
+                                                 const double* __restrict__ Cbuf) {
+    int nbk = np / GJ_B;
+    int ib = blockIdx.x / nbk, jb = blockIdx.x % nbk;
+    int wv = threadIdx.x / WAVE;
+    int qr = wv / 2, qc = wv % 2;
+    double* T = M + (int64_t)ib * GJ_B * np + jb * GJ_B;
+    if (ib == kb) {
+        if (jb == kb)
+            for (int e = threadIdx.x; e < GJ_B * GJ_B; e += 256)
+                T[(int64_t)(e / GJ_B) * np + e % GJ_B] = P[e];
+        return;
+    }
+    const double* X = Cbuf + (int64_t)ib * GJ_B * GJ_B;
+    if (jb == kb) {
+        d4v acc = tile_mm<MF>(X, GJ_B, P, GJ_B, qr, qc);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            int r, c;
+            tile_rc(i, qr, qc, r, c);
+            T[(int64_t)r * np + c] = -acc[i];
+        }
+    } else {
+        const double* Y = M + (int64_t)kb * GJ_B * np + jb * GJ_B;
+        d4v acc = tile_mm<MF>(X, GJ_B, Y, np, qr, qc);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            int r, c;
+            tile_rc(i, qr, qc, r, c);
+            T[(int64_t)r * np + c] -= acc[i];
+        }
+    }
+}
+
+// In-place inverse of the np x np row-major matrix M (np a multiple of 32).
+// P: 32x32 scratch, C: np x 32 scratch, bad: set to 1 on a zero pivot.
+void gj_invert(hipStream_t st, double* M, int np, double* P, double* C, int* bad) {
+    int nbk = np / GJ_B;
+    static const bool plain = getenv("DPSIM_GJ_PLAIN") != nullptr;
+    for (int kb = 0; kb < nbk; ++kb) {
+        gj_diag<<<1, 256, 0, st>>>(M, np, kb, P, bad);
+        if (plain) {
+            gj_row<false><<<2 * nbk, 256, 0, st>>>(M, np, kb, P, C);
+            gj_update<false><<<nbk * nbk, 256, 0, st>>>(M, np, kb, P, C);
+        } else {
+            gj_row<true><<<2 * nbk, 256, 0, st>>>(M, np, kb, P, C);
+            gj_update<true><<<nbk * nbk, 256, 0, st>>>(M, np, kb, P, C);
+        }
+    }
+    DP_LAUNCH_CHECK();
+}
+
+template <class T>
+__global__ void copy_inv(const double* __restrict__ M, int np, int n, T* out) {
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)n * n) return;
+    int r = (int)(idx / n), c = (int)(idx % n);
+    out[idx] = (T)M[(int64_t)r * np + c];
+}
+
+// ---------------------------------------------------------------------------
+// Setup driver
+// ---------------------------------------------------------------------------
+static void build_sell(dp_sim* s, const Csr& A, Sell& S, bool pad_self, Arena& H, Arena& Sc,
+                       const char* what) {
+    hipStream_t st = s->stream;
+    S.n = A.n;
+    S.nslices = (A.n + 63) / 64;
+    S.sptr = H.get<int>(S.nslices + 1, what);
+    size_t mark = Sc.top;
+    int64_t* w = Sc.get<int64_t>(S.nslices + 1, "sell widths");
+    int64_t* tmp = Sc.get<int64_t>(scan_tmp_size(S.nslices + 1), "sell scan");
+    int64_t total = 0;
+    if (S.nslices > 0) {
+        sell_width<<<ceil_div(S.nslices, 256), 256, 0, st>>>(A, S.nslices, w);
+        DP_LAUNCH_CHECK();
+        exclusive_scan(st, w, S.nslices, tmp, &total);
+    }
+    S.nel = total;
+    sell_ptr<<<ceil_div(S.nslices + 1, 256), 256, 0, st>>>(w, S.nslices, total, S.sptr);
+    DP_LAUNCH_CHECK();
+    S.col = H.get<int>(total, what);
+    if (s->fp32) {
+        S.val = H.get<float>(total, what);
+        if (S.nslices)
+            sell_fill<float><<<S.nslices, 64, 0, st>>>(A, S.sptr, pad_self, S.col, (float*)S.val);
+    } else {
+        S.val = H.get<double>(total, what);
+        if (S.nslices)
+            sell_fill<double><<<S.nslices, 64, 0, st>>>(A, S.sptr, pad_self, S.col, (double*)S.val);
+    }
+    DP_LAUNCH_CHECK();
+    Sc.top = mark;
+}
+
+static void level_apply_data(dp_sim* s, AmgLevel& L, Arena& H, Arena& Sc) {
+    size_t es = s->fp32 ? sizeof(float) : sizeof(double);
+    L.dinv = H.take(es * (L.n > 0 ? L.n : 1), "amg dinv");
+    L.x = H.take(es * (L.n > 0 ? L.n : 1), "amg x");
+    L.b = H.take(es * (L.n > 0 ? L.n : 1), "amg b");
+    L.r = H.take(es * (L.n > 0 ? L.n : 1), "amg r");
+    L.t = H.take(es * (L.n > 0 ? L.n : 1), "amg t");
+    if (L.n == 0) return;
+    if (s->fp32) l1_kernel<float><<<ceil_div(L.n, 256), 256, 0, s->stream>>>(L.A, (float*)L.dinv);
+    else l1_kernel<double><<<ceil_div(L.n, 256), 256, 0, s->stream>>>(L.A, (double*)L.dinv);
+    DP_LAUNCH_CHECK();
+}
+
+static void coarse_inverse(dp_sim* s, const Csr& A, Arena& H, Arena& Sc) {
+    hipStream_t st = s->stream;
+    int n = A.n;
+    s->coarse_n = n;
+    if (n == 0) return;
+    int np = ((n + GJ_B - 1) / GJ_B) * GJ_B;
+    size_t mark = Sc.top;
+    double* M = Sc.get<double>((int64_t)np * np, "coarse dense");
+    double* P = Sc.get<double>(GJ_B * GJ_B, "coarse pivot block");
+    double* C = Sc.get<double>((int64_t)np * GJ_B, "coarse column panel");
+    int* bad = Sc.get<int>(1, "coarse flag");
+    DP_HIP(hipMemsetAsync(bad, 0, sizeof(int), st));
+    dense_fill<<<ceil_div((int64_t)np * np, 256), 256, 0, st>>>(A, np, M);
+    DP_LAUNCH_CHECK();
+    gj_invert(st, M, np, P, C, bad);
+    if (s->fp32) {
+        s->coarse_inv = H.get<float>((int64_t)n * n, "coarse inverse");
+        copy_inv<float><<<ceil_div((int64_t)n * n, 256), 256, 0, st>>>(M, np, n, (float*)s->coarse_inv);
+    } else {
+        s->coarse_inv = H.get<double>((int64_t)n * n, "coarse inverse");
+        copy_inv<double><<<ceil_div((int64_t)n * n, 256), 256, 0, st>>>(M, np, n, (double*)s->coarse_inv);
+    }
+    DP_LAUNCH_CHECK();
+    int hbad = 0;
+    DP_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    DP_HIP(hipStreamSynchronize(st));
+    if (hbad) fail(DP_E_NUMERIC, "zero pivot in the coarsest-level dense inverse");
+    Sc.top = mark;
+}
+
+void amg_setup(dp_sim* s) {
+    hipStream_t st = s->stream;
+    Arena& H = s->hier;
+    Arena& Sc = s->scr;
+    H.top = 0;
+    Sc.top = 0;
+    s->levels.clear();
+    s->coarse_inv = nullptr;
+    s->coarse_n = 0;
+    const dp_sim_desc& d = s->desc;
+    Csr A = s->Ap0;
+    for (;;) {
+        AmgLevel L;
+        L.n = A.n;
+        L.A = A;
+        level_apply_data(s, L, H, Sc);
+        bool last = (A.n <= d.amg_coarse_max) || ((int)s->levels.size() + 1 >= d.amg_max_levels);
+        int n = A.n;
+        int nc = 0;
+        int64_t* cidx = nullptr;
+        unsigned char* smask = nullptr;
+        double* diag = nullptr;
+        size_t smark = Sc.top;
+        if (!last) {
+            // strength + PMIS
+            smask = Sc.get<unsigned char>(A.nnz, "strength mask");
+            int* nst = Sc.get<int>(n, "nst");
+            diag = Sc.get<double>(n, "diag");
+            int* state = Sc.get<int>(n, "pmis state");
+            double* wgt = Sc.get<double>(n, "pmis weight");
+            int* beaten = Sc.get<int>(n, "pmis beaten");
+            int* und = Sc.get<int>(1, "pmis count");
+            cidx = Sc.get<int64_t>(n + 1, "coarse index");
+            int64_t* stmp = Sc.get<int64_t>(scan_tmp_size(n + 1), "scan tmp");
+            L.cf = H.get<int>(n, "cf");
+            DP_HIP(hipMemsetAsync(nst, 0, sizeof(int) * n, st));
+            DP_HIP(hipMemsetAsync(beaten, 0xff, sizeof(int) * n, st));
+            strength_kernel<<<ceil_div(n, 256), 256, 0, st>>>(A, d.amg_theta, smask, nst, diag);
+            pmis_init<<<ceil_div(n, 256), 256, 0, st>>>(n, nst, state, wgt);
+            DP_LAUNCH_CHECK();
+            for (int iter = 0;; ++iter) {
+                if (iter > 10000) fail(DP_E_NUMERIC, "PMIS did not terminate");
+                DP_HIP(hipMemsetAsync(und, 0, sizeof(int), st));
+                pmis_beat<<<ceil_div(n, 256), 256, 0, st>>>(A, smask, state, wgt, iter, beaten);
+                pmis_select<<<ceil_div(n, 256), 256, 0, st>>>(n, state, beaten, iter);
+                pmis_fpass<<<ceil_div(n, 256), 256, 0, st>>>(A, smask, state, iter, und);
+                DP_LAUNCH_CHECK();
+                int hu = 0;
+                DP_HIP(hipMemcpyAsync(&hu, und, sizeof(int), hipMemcpyDeviceToHost, st));
+                DP_HIP(hipStreamSynchronize(st));
+                if (hu == 0) break;
+            }
+            pmis_final<<<ceil_div(n, 256), 256, 0, st>>>(n, state, L.cf, cidx);
+            DP_LAUNCH_CHECK();
+            int64_t tot = 0;
+            exclusive_scan(st, cidx, n, stmp, &tot);
+            nc = (int)tot;
+            if (nc == 0 || nc >= n) last = true;
+        }
+        if (last) {
+            Sc.top = smark;
+            L.cf = nullptr;
+            coarse_inverse(s, A, H, Sc);
+            s->levels.push_back(L);
+            break;
+        }
+        // interpolation
+        {
+            double* beta = Sc.get<double>(n, "beta");
+            int* g = Sc.get<int>(n, "g");
+            double* dd = Sc.get<double>(n, "d");
+            int64_t* cnt = Sc.get<int64_t>(n + 1, "interp count");
+            int64_t* stmp = Sc.get<int64_t>(scan_tmp_size(n + 1), "scan tmp");
+            interp_beta<<<ceil_div(n, 256), 256, 0, st>>>(A, smask, L.cf, diag, beta, g);
+            interp_count<<<ceil_div(n, 256), 256, 0, st>>>(A, smask, L.cf, diag, beta, g, dd, cnt);
+            DP_LAUNCH_CHECK();
+            int64_t m = 0;
+            exclusive_scan(st, cnt, n, stmp, &m);
+            int cbits = bits_for(nc);
+            int rbits = bits_for(n);
+            uint64_t* k0 = Sc.get<uint64_t>(m, "interp keys");
+            double* v0 = Sc.get<double>(m, "interp vals");
+            uint64_t* k1 = Sc.get<uint64_t>(m, "interp keys");
+            double* v1 = Sc.get<double>(m, "interp vals");
+            int64_t* rtmp = Sc.get<int64_t>(sort_tmp_size(m), "sort tmp");
+            interp_expand<<<ceil_div(n, 256), 256, 0, st>>>(A, smask, L.cf, cidx, diag, beta, cnt, cbits,
+                                                            k0, v0);
+            DP_LAUNCH_CHECK();
+            int which = radix_sort(st, k0, v0, k1, v1, m, rbits + cbits, rtmp);
+            uint64_t* ks = which ? k1 : k0;
+            double* vs = which ? v1 : v0;
+            int64_t* flag = Sc.get<int64_t>(m, "rbk flag");
+            double* sums = Sc.get<double>(m, "rbk sums");
+            int* rowkey = Sc.get<int>(m, "rbk rows");
+            Csr W;
+            W.ncols = nc;
+            reduce_to_csr(st, ks, vs, m, cbits, n, flag, sums, rowkey, rtmp, Sc, W, "interp W");
+            // truncation into P
+            int64_t* pc = Sc.get<int64_t>(n + 1, "P count");
+            pcount_kernel<<<ceil_div(n, 256), 256, 0, st>>>(W, L.cf, dd, d.amg_trunc, pc);
+            DP_LAUNCH_CHECK();
+            int64_t pn = 0;
+            exclusive_scan(st, pc, n, stmp, &pn);
+            L.P.n = n;
+            L.P.ncols = nc;
+            L.P.nnz = pn;
+            L.P.rowptr = H.get<int>(n + 1, "P rowptr");
+            L.P.col = H.get<int>(pn, "P col");
+            L.P.val = H.get<double>(pn, "P val");
+            i64_to_i32<<<ceil_div(n + 1, 256), 256, 0, st>>>(pc, n, pn, L.P.rowptr);
+            pfill_kernel<<<ceil_div(n, 256), 256, 0, st>>>(W, L.cf, cidx, dd, d.amg_trunc, pc, L.P.col,
+                                                           L.P.val);
+            DP_LAUNCH_CHECK();
+        }
+        Sc.top = smark;
+        // R = P^T
+        Csr R;
+        {
+            int64_t m = L.P.nnz;
+            int rbits = bits_for(n);
+            int cb = bits_for(nc);
+            uint64_t* k0 = Sc.get<uint64_t>(m, "PT keys");
+            double* v0 = Sc.get<double>(m, "PT vals");
+            uint64_t* k1 = Sc.get<uint64_t>(m, "PT keys");
+            double* v1 = Sc.get<double>(m, "PT vals");
+            int64_t* rtmp = Sc.get<int64_t>(sort_tmp_size(m) + scan_tmp_size(m + 1), "sort tmp");
+            transpose_expand<<<ceil_div(n, 256), 256, 0, st>>>(L.P, rbits, k0, v0);
+            DP_LAUNCH_CHECK();
+            int which = radix_sort(st, k0, v0, k1, v1, m, rbits + cb, rtmp);
+            int64_t* flag = Sc.get<int64_t>(m, "rbk flag");
+            double* sums = Sc.get<double>(m, "rbk sums");
+            int* rowkey = Sc.get<int>(m, "rbk rows");
+            R.ncols = n;
+            reduce_to_csr(st, which ? k1 : k0, which ? v1 : v0, m, rbits, nc, flag, sums, rowkey, rtmp,
+                          H, R, "R");
+        }
+        Sc.top = smark;
+        // Galerkin A_c = R A P
+        Csr Ac;
+        {
+            int64_t* cnt = Sc.get<int64_t>(n + 1, "rap count");
+            int64_t* stmp = Sc.get<int64_t>(scan_tmp_size(n + 1), "scan tmp");
+            rap_count<<<ceil_div(n, 256), 256, 0, st>>>(A, L.P, cnt);
+            DP_LAUNCH_CHECK();
+            int64_t m = 0;
+            exclusive_scan(st, cnt, n, stmp, &m);
+            int cb = bits_for(nc);
+            uint64_t* k0 = Sc.get<uint64_t>(m, "rap keys");
+            double* v0 = Sc.get<double>(m, "rap vals");
+            uint64_t* k1 = Sc.get<uint64_t>(m, "rap keys");
+            double* v1 = Sc.get<double>(m, "rap vals");
+            int64_t* rtmp = Sc.get<int64_t>(sort_tmp_size(m) + scan_tmp_size(m + 1), "sort tmp");
+            rap_expand<<<ceil_div(n, 256), 256, 0, st>>>(A, L.P, cnt, cb, k0, v0);
+            DP_LAUNCH_CHECK();
+            int which = radix_sort(st, k0, v0, k1, v1, m, 2 * cb, rtmp);
+            int64_t* flag = Sc.get<int64_t>(m, "rbk flag");
+            double* sums = Sc.get<double>(m, "rbk sums");
+            int* rowkey = Sc.get<int>(m, "rbk rows");
+            Ac.ncols = nc;
+            reduce_to_csr(st, which ? k1 : k0, which ? v1 : v0, m, cb, nc, flag, sums, rowkey, rtmp, H,
+                          Ac, "coarse A");
+        }
+        Sc.top = smark;
+        L.nc = nc;
+        build_sell(s, A, L.As, true, H, Sc, "A sell");
+        build_sell(s, L.P, L.Ps, false, H, Sc, "P sell");
+        build_sell(s, R, L.Rs, false, H, Sc, "R sell");
+        s->levels.push_back(L);
+        A = Ac;
+    }
+    // the coarsest level's operator is only used through its dense inverse
+}
+
+// ---------------------------------------------------------------------------
+// V(1,1) cycle
+// ---------------------------------------------------------------------------
+enum { SV_Y = 0, SV_PRE = 1, SV_PROL = 2, SV_POST = 3 };
+
+template <class T, int MODE>
+__global__ void __launch_bounds__(256) sell_kernel(const int* __restrict__ sptr, const int* __restrict__ col,
+                                                   const T* __restrict__ val, int n,
+                                                   const T* __restrict__ dinv, const T* __restrict__ b,
+                                                   const T* __restrict__ x, T* y, T* y2) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    int s = r >> 6, lane = r & 63;
+    int base = sptr[s];
+    int w = (sptr[s + 1] - base) >> 6;
+    T acc = 0;
+    for (int k = 0; k < w; ++k) {
+        int e = base + (k << 6) + lane;
+        int c = col[e];
+        T v = val[e];
+        if (MODE == SV_PRE) acc += v * (dinv[c] * b[c]);
+        else acc += v * x[c];
+    }
+    if (MODE == SV_Y) {
+        y[r] = acc;
+    } else if (MODE == SV_PRE) {  // y = dinv b (smoothed x from zero), y2 = b - A y
+        y[r] = dinv[r] * b[r];
+        y2[r] = b[r] - acc;
+    } else if (MODE == SV_PROL) {  // y += P x
+        y[r] += acc;
+    } else {  // y = x + dinv (b - A x)
+        y[r] = x[r] + dinv[r] * (b[r] - acc);
+    }
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) dense_gemv(const T* __restrict__ M, int n, const T* __restrict__ b,
+                                                  T* y) {
+    int row = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    int lane = threadIdx.x % WAVE;
+    if (row >= n) return;
+    T acc = 0;
+    for (int c = lane; c < n; c += WAVE) acc += M[(int64_t)row * n + c] * b[c];
+    acc = wave_sum(acc);
+    if (lane == 0) y[row] = acc;
+}
+
+template <class T, int MODE>
+static void sell_launch(dp_sim* s, const Sell& S, const T* dinv, const T* b, const T* x, T* y, T* y2) {
+    if (S.n == 0) return;
+    sell_kernel<T, MODE><<<ceil_div(S.n, 256), 256, 0, s->stream>>>(S.sptr, S.col, (const T*)S.val, S.n,
+                                                                    dinv, b, x, y, y2);
+    DP_LAUNCH_CHECK();
+}
+
+template <class T>
+T* amg_vcycle(dp_sim* s) {
+    int L = (int)s->levels.size();
+    for (int l = 0; l < L - 1; ++l) {
+        AmgLevel& lv = s->levels[l];
+        sell_launch<T, SV_PRE>(s, lv.As, (T*)lv.dinv, (T*)lv.b, nullptr, (T*)lv.x, (T*)lv.r);
+        sell_launch<T, SV_Y>(s, lv.Rs, nullptr, nullptr, (T*)lv.r, (T*)s->levels[l + 1].b, nullptr);
+    }
+    AmgLevel& co = s->levels[L - 1];
+    if (co.n > 0) {
+        dense_gemv<T><<<ceil_div(co.n, 256 / WAVE), 256, 0, s->stream>>>((const T*)s->coarse_inv, co.n,
+                                                                        (T*)co.b, (T*)co.x);
+        DP_LAUNCH_CHECK();
+    }
+    T* xs = (T*)co.x;
+    for (int l = L - 2; l >= 0; --l) {
+        AmgLevel& lv = s->levels[l];
+        sell_launch<T, SV_PROL>(s, lv.Ps, nullptr, nullptr, xs, (T*)lv.x, nullptr);
+        sell_launch<T, SV_POST>(s, lv.As, (T*)lv.dinv, (T*)lv.b, (T*)lv.x, (T*)lv.t, nullptr);
+        xs = (T*)lv.t;
+    }
+    return xs;
+}
+template double* amg_vcycle<double>(dp_sim*);
+template float* amg_vcycle<float>(dp_sim*);
+
+}  // namespace dp
+
+// ---------------------------------------------------------------------------
+// Test hooks: one preconditioner stage, dense inverse self-test
+// ---------------------------------------------------------------------------
+extern "C" dp_status dp_selftest_dense_inverse(const double* a, int32_t n, double* ainv, void* d_ws,
+                                                size_t bytes, void* stream) {
+    using namespace dp;
+    if (!a || !ainv || !d_ws || n <= 0 || n > 4096) return DP_E_INVALID;
+    try {
+        hipStream_t st = (hipStream_t)stream;
+        int np = ((n + GJ_B - 1) / GJ_B) * GJ_B;
+        Arena ar;
+        ar.base = (char*)d_ws;
+        ar.cap = bytes;
+        double* M = ar.get<double>((int64_t)np * np, "dense matrix");
+        double* P = ar.get<double>(GJ_B * GJ_B, "pivot block");
+        double* C = ar.get<double>((int64_t)np * GJ_B, "column panel");
+        int* bad = ar.get<int>(1, "flag");
+        std::vector<double> h((size_t)np * np, 0.0);
+        for (int r = 0; r < np; ++r)
+            for (int c = 0; c < np; ++c)
+                h[(size_t)r * np + c] = (r < n && c < n) ? a[(size_t)r * n + c] : (r == c ? 1.0 : 0.0);
+        DP_HIP(hipMemcpyAsync(M, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, st));
+        DP_HIP(hipMemsetAsync(bad, 0, sizeof(int), st));
+        gj_invert(st, M, np, P, C, bad);
+        int hb = 0;
+        DP_HIP(hipMemcpyAsync(h.data(), M, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
+        DP_HIP(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+        DP_HIP(hipStreamSynchronize(st));
+        for (int r = 0; r < n; ++r)
+            for (int c = 0; c < n; ++c) ainv[(size_t)r * n + c] = h[(size_t)r * np + c];
+        return hb ? DP_E_NUMERIC : DP_OK;
+    } catch (const Error& e) {
+        return e.code;
+    }
+}

@@ -1,0 +1,58 @@
+// Host-side launchers of the device kernels (one stream per handle).
+#pragma once
+
+#include "sim.h"
+
+namespace dp {
+
+struct Phys;
+Phys make_phys(const dp_sim* s);
+
+// assemble.hip
+void launch_geometry(dp_sim* s, const double* kx, const double* ky, const double* kz,
+                     const double* km, const double* phi_f, const double* phi_m,
+                     const int* perf_cell, const double* perf_rw, const double* perf_skin);
+void launch_accumulation(dp_sim* s, const d2* x, d2* acc);
+void launch_assemble(dp_sim* s, double dt);
+double residual_norm(dp_sim* s, double dt);
+void launch_newton_update(dp_sim* s);
+
+// linalg.hip
+void launch_decouple(dp_sim* s);
+template <class T> void bspmv(dp_sim* s, const V2<T>* x, V2<T>* y);
+template <class T> void bresidual(dp_sim* s, const V2<T>* b, const V2<T>* x, V2<T>* y);
+template <class T> void bresidual_p(dp_sim* s, const V2<T>* b, const V2<T>* x, T* yp);
+template <class T>
+void bresidual_prol(dp_sim* s, const V2<T>* b, const V2<T>* x, const T* e, V2<T>* x2, V2<T>* y);
+template <class T> void ilu_factor(dp_sim* s);
+template <class T> void ilu_solve(dp_sim* s, const V2<T>* r, V2<T>* z);
+
+// krylov.hip (FP64 vectors of length len doubles)
+void vec_copy(dp_sim* s, const double* x, double* y, int64_t len);
+void vec_zero(dp_sim* s, double* x, int64_t len);
+void vec_scale_to(dp_sim* s, const double* x, double alpha, double* y, int64_t len);
+void vec_axpy(dp_sim* s, double alpha, const double* x, double* y, int64_t len);
+void to_f32(dp_sim* s, const double* x, float* y, int64_t len);
+void to_f64(dp_sim* s, const float* x, double* y, int64_t len);
+void add_to_f64(dp_sim* s, const float* a, const float* b, double* y, int64_t len);
+template <class T> void vec_add3(dp_sim* s, const T* a, const T* b, T* y, int64_t len);
+// reductions: results land in s->red_out (device) and are copied to s->red_host
+void dot_multi(dp_sim* s, const double* V, int64_t ld, int k, const double* w, int64_t len, double* out);
+void cgs_update_dot(dp_sim* s, const double* V, int64_t ld, int k, const double* h, double* w,
+                    int64_t len, double* out);
+void cgs_update_norm(dp_sim* s, const double* V, int64_t ld, int k, const double* h, double* w,
+                     int64_t len, double* out);
+void norm2(dp_sim* s, const double* x, int64_t len, double* out);
+void combine(dp_sim* s, const double* Z, int64_t ld, int k, const double* y, double* x, int64_t len);
+
+// amg.hip
+void amg_extract_level0(dp_sim* s);
+void amg_setup(dp_sim* s);
+template <class T> T* amg_vcycle(dp_sim* s);  // solves levels[0] with b = levels[0].b; returns x
+void amg_release(dp_sim* s);
+
+// cpr.hip
+void cpr_setup(dp_sim* s);
+void cpr_apply(dp_sim* s, const double* r, double* z);  // FP64 in/out, [2nb]
+
+}  // namespace dp

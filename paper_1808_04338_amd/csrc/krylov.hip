@@ -1,0 +1,214 @@
+// Vector kernels of the GMRES iteration: classical Gram-Schmidt passes fused
+// with their dot products, norms, the solution update, and precision casts.
+//
+// Reductions are deterministic: every block writes its partial sums, and the
+// last block to finish (ticket counter) adds them in block order.
+#include "kernels.h"
+
+namespace dp {
+
+constexpr int KMAX = 32;  // restart <= 30: at most 31 basis vectors
+constexpr int RBLK = 256;
+constexpr int MAX_RED_BLOCKS = 1024;
+
+struct Coef {
+    double c[KMAX];
+};
+
+__device__ inline double block_sum(double v, double* sh) {
+    v = wave_sum(v);
+    __syncthreads();
+    if (threadIdx.x % WAVE == 0) sh[threadIdx.x / WAVE] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int i = 0; i < RBLK / WAVE; ++i) s += sh[i];
+    return s;
+}
+
+// OP 0: out_k = V_k . w                           (k < nv)
+// OP 1: w -= sum_k h_k V_k; out_k = V_k . w        (one read of every V_k)
+// OP 2: w -= sum_k h_k V_k; out_0 = w . w
+// OP 3: out_0 = w . w
+template <int OP>
+__global__ void __launch_bounds__(RBLK) red_kernel(const double* __restrict__ V, int64_t ld, int nv,
+                                                   const double* __restrict__ h, double* w, int64_t len,
+                                                   double* part, unsigned int* count, double* out) {
+    __shared__ double sh[RBLK / WAVE];
+    __shared__ bool last;
+    double acc[KMAX];
+    double hh[KMAX];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        acc[k] = 0.0;
+        hh[k] = (OP == 1 || OP == 2) && k < nv ? h[k] : 0.0;
+    }
+    const int64_t stride = (int64_t)gridDim.x * RBLK;
+    for (int64_t i = (int64_t)blockIdx.x * RBLK + threadIdx.x; i < len; i += stride) {
+        double wi = w[i];
+        if (OP == 0) {
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k)
+                if (k < nv) acc[k] += V[k * ld + i] * wi;
+        } else if (OP == 1) {
+            double v[KMAX];
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k) v[k] = k < nv ? V[k * ld + i] : 0.0;
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k)
+                if (k < nv) wi -= hh[k] * v[k];
+            w[i] = wi;
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k)
+                if (k < nv) acc[k] += v[k] * wi;
+        } else if (OP == 2) {
+#pragma unroll
+            for (int k = 0; k < KMAX; ++k)
+                if (k < nv) wi -= hh[k] * V[k * ld + i];
+            w[i] = wi;
+            acc[0] += wi * wi;
+        } else {
+            acc[0] += wi * wi;
+        }
+    }
+    const int nres = (OP == 0 || OP == 1) ? nv : 1;
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+        if (k < nres) {
+            double s = block_sum(acc[k], sh);
+            if (threadIdx.x == 0) part[(int64_t)blockIdx.x * KMAX + k] = s;
+        }
+    }
+    if (threadIdx.x == 0) {
+        __threadfence();
+        unsigned int ticket = atomicAdd(count, 1u);
+        last = (ticket == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+    for (int k = 0; k < nres; ++k) {
+        double v = 0.0;
+        for (int b = threadIdx.x; b < (int)gridDim.x; b += RBLK) v += part[(int64_t)b * KMAX + k];
+        double s = block_sum(v, sh);
+        if (threadIdx.x == 0) out[k] = s;
+    }
+    if (threadIdx.x == 0) *count = 0u;
+}
+
+static int red_grid(int64_t len) {
+    int64_t g = (len + RBLK * 4 - 1) / (RBLK * 4);
+    if (g < 1) g = 1;
+    if (g > MAX_RED_BLOCKS) g = MAX_RED_BLOCKS;
+    return (int)g;
+}
+
+template <int OP>
+static void red_launch(dp_sim* s, const double* V, int64_t ld, int nv, const double* h, double* w,
+                       int64_t len, double* out) {
+    if (nv > KMAX) fail(DP_E_INVALID, "too many Krylov vectors");
+    int g = red_grid(len);
+    red_kernel<OP><<<g, RBLK, 0, s->stream>>>(V, ld, nv, h, w, len, s->red_part, s->red_count, out);
+    DP_LAUNCH_CHECK();
+}
+
+void dot_multi(dp_sim* s, const double* V, int64_t ld, int k, const double* w, int64_t len, double* out) {
+    red_launch<0>(s, V, ld, k, nullptr, const_cast<double*>(w), len, out);
+}
+void cgs_update_dot(dp_sim* s, const double* V, int64_t ld, int k, const double* h, double* w,
+                    int64_t len, double* out) {
+    red_launch<1>(s, V, ld, k, h, w, len, out);
+}
+void cgs_update_norm(dp_sim* s, const double* V, int64_t ld, int k, const double* h, double* w,
+                     int64_t len, double* out) {
+    red_launch<2>(s, V, ld, k, h, w, len, out);
+}
+void norm2(dp_sim* s, const double* x, int64_t len, double* out) {
+    red_launch<3>(s, nullptr, 0, 1, nullptr, const_cast<double*>(x), len, out);
+}
+
+// x += sum_k y_k Z_k
+__global__ void combine_kernel(const double* __restrict__ Z, int64_t ld, int k, Coef y, double* x,
+                               int64_t len) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= len) return;
+    double acc = x[i];
+#pragma unroll
+    for (int j = 0; j < KMAX; ++j)
+        if (j < k) acc += y.c[j] * Z[j * ld + i];
+    x[i] = acc;
+}
+
+void combine(dp_sim* s, const double* Z, int64_t ld, int k, const double* y, double* x, int64_t len) {
+    Coef c{};
+    for (int j = 0; j < k && j < KMAX; ++j) c.c[j] = y[j];
+    combine_kernel<<<ceil_div(len, 256), 256, 0, s->stream>>>(Z, ld, k, c, x, len);
+    DP_LAUNCH_CHECK();
+}
+
+__global__ void scale_kernel(const double* __restrict__ x, double a, double* y, int64_t len) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < len) y[i] = a * x[i];
+}
+__global__ void axpy_kernel(double a, const double* __restrict__ x, double* y, int64_t len) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < len) y[i] += a * x[i];
+}
+__global__ void zero_kernel(double* x, int64_t len) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < len) x[i] = 0.0;
+}
+__global__ void f32_kernel(const double* __restrict__ x, float* y, int64_t len) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < len) y[i] = (float)x[i];
+}
+__global__ void f64_kernel(const float* __restrict__ x, double* y, int64_t len) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < len) y[i] = (double)x[i];
+}
+__global__ void add_f64_kernel(const float* __restrict__ a, const float* __restrict__ b, double* y,
+                               int64_t len) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < len) y[i] = (double)(a[i] + b[i]);
+}
+template <class T>
+__global__ void add3_kernel(const T* __restrict__ a, const T* __restrict__ b, T* y, int64_t len) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < len) y[i] = a[i] + b[i];
+}
+
+void vec_copy(dp_sim* s, const double* x, double* y, int64_t len) {
+    DP_HIP(hipMemcpyAsync(y, x, sizeof(double) * len, hipMemcpyDeviceToDevice, s->stream));
+}
+void vec_zero(dp_sim* s, double* x, int64_t len) {
+    zero_kernel<<<ceil_div(len, 256), 256, 0, s->stream>>>(x, len);
+    DP_LAUNCH_CHECK();
+}
+void vec_scale_to(dp_sim* s, const double* x, double alpha, double* y, int64_t len) {
+    scale_kernel<<<ceil_div(len, 256), 256, 0, s->stream>>>(x, alpha, y, len);
+    DP_LAUNCH_CHECK();
+}
+void vec_axpy(dp_sim* s, double alpha, const double* x, double* y, int64_t len) {
+    axpy_kernel<<<ceil_div(len, 256), 256, 0, s->stream>>>(alpha, x, y, len);
+    DP_LAUNCH_CHECK();
+}
+void to_f32(dp_sim* s, const double* x, float* y, int64_t len) {
+    f32_kernel<<<ceil_div(len, 256), 256, 0, s->stream>>>(x, y, len);
+    DP_LAUNCH_CHECK();
+}
+void to_f64(dp_sim* s, const float* x, double* y, int64_t len) {
+    f64_kernel<<<ceil_div(len, 256), 256, 0, s->stream>>>(x, y, len);
+    DP_LAUNCH_CHECK();
+}
+void add_to_f64(dp_sim* s, const float* a, const float* b, double* y, int64_t len) {
+    add_f64_kernel<<<ceil_div(len, 256), 256, 0, s->stream>>>(a, b, y, len);
+    DP_LAUNCH_CHECK();
+}
+template <class T>
+void vec_add3(dp_sim* s, const T* a, const T* b, T* y, int64_t len) {
+    add3_kernel<T><<<ceil_div(len, 256), 256, 0, s->stream>>>(a, b, y, len);
+    DP_LAUNCH_CHECK();
+}
+template void vec_add3<double>(dp_sim*, const double*, const double*, double*, int64_t);
+template void vec_add3<float>(dp_sim*, const float*, const float*, float*, int64_t);
+
+}  // namespace dp

@@ -1,0 +1,558 @@
+// Decoupling, block sparse matrix-vector products and block ILU(0).
+//
+// Every kernel covers the three row groups of the elimination order in one
+// launch: blocks [0, bm) take matrix rows, [bm, bm+bf) fracture rows and the
+// last nw blocks one well each.  A thread owns one row and writes only it.
+#include "kernels.h"
+
+namespace dp {
+
+// ---------------------------------------------------------------------------
+// Decoupling D^-1 J, D^-1 b (Eq. (14)): in each node row, row0 -= (a01/a11) row1
+// with a = J_ii.  Well rows are copied.  b = -R.
+// ---------------------------------------------------------------------------
+struct DecArgs {
+    BMat<double> J, A;
+    BMat<float> A32;
+    bool f32;
+    const d2* R;
+    d2* b;
+    const int* fmask;
+    const int* fperf;
+    const int* well_ptr;
+    int n, nw;
+};
+
+__device__ inline void dec_pair(const d2* s0, const d2* s1, d2* o0, d2* o1, float2* p0, float2* p1,
+                                int64_t i, double f, bool f32) {
+    d2 r0 = s0[i], r1 = s1[i];
+    d2 a0 = mk2(r0.x - f * r1.x, r0.y - f * r1.y);
+    o0[i] = a0;
+    o1[i] = r1;
+    if (f32) {
+        p0[i] = make_float2((float)a0.x, (float)a0.y);
+        p1[i] = make_float2((float)r1.x, (float)r1.y);
+    }
+}
+
+__global__ void __launch_bounds__(256) decouple_kernel(DecArgs a, int bm, int bf) {
+    int b = blockIdx.x;
+    int n = a.n;
+    float2* n0 = nullptr;
+    bool f32 = a.f32;
+#define F32P(p) (f32 ? (float2*)(p) : n0)
+    if (b < bm + bf) {
+        int pos = b * blockDim.x + threadIdx.x - (b < bm ? 0 : bm * (int)blockDim.x);
+        bool frac = b >= bm;
+        if (pos >= n) return;
+        int row = frac ? n + pos : pos;
+        d2 d0 = a.J.d0[row], d1 = a.J.d1[row];
+        double f = d0.y / d1.y;
+        dec_pair(a.J.d0, a.J.d1, a.A.d0, a.A.d1, F32P(a.A32.d0), F32P(a.A32.d1), row, f, f32);
+        d2 r = a.R[row];
+        double b0 = -r.x, b1 = -r.y;
+        a.b[row] = mk2(b0 - f * b1, b1);
+        if (!frac) {
+            dec_pair(a.J.m0, a.J.m1, a.A.m0, a.A.m1, F32P(a.A32.m0), F32P(a.A32.m1), pos, f, f32);
+        } else {
+            for (int s = 0; s < 7; ++s)
+                dec_pair(a.J.f0, a.J.f1, a.A.f0, a.A.f1, F32P(a.A32.f0), F32P(a.A32.f1),
+                         (int64_t)s * n + pos, f, f32);
+            int p = a.fperf[pos];
+            if (p >= 0)
+                dec_pair(a.J.fw0, a.J.fw1, a.A.fw0, a.A.fw1, F32P(a.A32.fw0), F32P(a.A32.fw1), p, f,
+                         f32);
+        }
+    } else {
+        int w = b - bm - bf;
+        int row = 2 * n + w;
+        if (threadIdx.x == 0) {
+            dec_pair(a.J.d0, a.J.d1, a.A.d0, a.A.d1, F32P(a.A32.d0), F32P(a.A32.d1), row, 0.0, f32);
+            d2 r = a.R[row];
+            a.b[row] = mk2(-r.x, -r.y);
+        }
+        for (int p = a.well_ptr[w] + threadIdx.x; p < a.well_ptr[w + 1]; p += blockDim.x)
+            dec_pair(a.J.wf0, a.J.wf1, a.A.wf0, a.A.wf1, F32P(a.A32.wf0), F32P(a.A32.wf1), p, 0.0, f32);
+    }
+#undef F32P
+}
+
+void launch_decouple(dp_sim* s) {
+    Topo& t = s->topo;
+    DecArgs a;
+    a.J = s->J;
+    a.A = s->A;
+    a.A32 = s->A32;
+    a.f32 = s->fp32;
+    a.R = s->res;
+    a.b = s->rhs;
+    a.fmask = nullptr;
+    a.fperf = t.fperf;
+    a.well_ptr = t.well_ptr;
+    a.n = t.n;
+    a.nw = t.nw;
+    int bm = ceil_div(t.n, 256);
+    decouple_kernel<<<2 * bm + t.nw, 256, 0, s->stream>>>(a, bm, bm);
+    DP_LAUNCH_CHECK();
+}
+
+// ---------------------------------------------------------------------------
+// Block SpMV.  MODE_Y: y = A x.  MODE_RES: y = b - A x.  MODE_RESP: yp = first
+// component of b - A x (reads only the pressure-row planes).  MODE_PROL:
+// x2 = x + (e, 0) (pressure correction prolonged from the AMG), y = b - A x2,
+// x2 written out.
+// ---------------------------------------------------------------------------
+enum { MODE_Y = 0, MODE_RES = 1, MODE_RESP = 2, MODE_PROL = 3 };
+
+template <class T>
+struct SpArgs {
+    BMat<T> A;
+    const V2<T>* x;
+    const V2<T>* b;
+    const T* e;     // MODE_PROL: [nb] pressure correction
+    V2<T>* y;       // MODE_Y/RES/PROL
+    T* yp;          // MODE_RESP
+    V2<T>* x2;      // MODE_PROL
+    const int* fcol;
+    const int* fcell;
+    const int* frow;
+    const int* fperf;
+    const int* perf_q;
+    const int* perf_well;
+    const int* well_ptr;
+    int n, nw;
+};
+
+template <class T, int MODE>
+__device__ inline V2<T> xval(const SpArgs<T>& a, int pos) {
+    V2<T> v = a.x[pos];
+    if (MODE == MODE_PROL) v.x += a.e[pos];
+    return v;
+}
+
+template <class T, int MODE>
+__device__ inline void acc_blk(const V2<T>* p0, const V2<T>* p1, int64_t i, V2<T> v, T& y0, T& y1) {
+    V2<T> r0 = p0[i];
+    y0 += r0.x * v.x + r0.y * v.y;
+    if (MODE != MODE_RESP) {
+        V2<T> r1 = p1[i];
+        y1 += r1.x * v.x + r1.y * v.y;
+    }
+}
+
+template <class T, int MODE>
+__device__ inline void sp_store(const SpArgs<T>& a, int row, T y0, T y1, V2<T> xself) {
+    if (MODE == MODE_Y) {
+        a.y[row] = mk2<T>(y0, y1);
+    } else if (MODE == MODE_RES) {
+        V2<T> bb = a.b[row];
+        a.y[row] = mk2<T>(bb.x - y0, bb.y - y1);
+    } else if (MODE == MODE_RESP) {
+        a.yp[row] = a.b[row].x - y0;
+    } else {
+        V2<T> bb = a.b[row];
+        a.y[row] = mk2<T>(bb.x - y0, bb.y - y1);
+        a.x2[row] = xself;
+    }
+}
+
+template <class T, int MODE>
+__global__ void __launch_bounds__(256) spmv_kernel(SpArgs<T> a, int bm, int bf) {
+    __shared__ T sh0[256 / WAVE], sh1[256 / WAVE];
+    int b = blockIdx.x;
+    int n = a.n;
+    if (b < bm) {
+        int c = b * blockDim.x + threadIdx.x;
+        if (c >= n) return;
+        T y0 = 0, y1 = 0;
+        V2<T> xs = xval<T, MODE>(a, c);
+        acc_blk<T, MODE>(a.A.d0, a.A.d1, c, xs, y0, y1);
+        acc_blk<T, MODE>(a.A.m0, a.A.m1, c, xval<T, MODE>(a, n + a.frow[c]), y0, y1);
+        sp_store<T, MODE>(a, c, y0, y1, xs);
+    } else if (b < bm + bf) {
+        int q = (b - bm) * blockDim.x + threadIdx.x;
+        if (q >= n) return;
+        int row = n + q;
+        T y0 = 0, y1 = 0;
+        V2<T> xs = xval<T, MODE>(a, row);
+        acc_blk<T, MODE>(a.A.d0, a.A.d1, row, xs, y0, y1);
+#pragma unroll
+        for (int s = 0; s < 6; ++s)
+            acc_blk<T, MODE>(a.A.f0, a.A.f1, (int64_t)s * n + q, xval<T, MODE>(a, a.fcol[s * n + q]), y0, y1);
+        acc_blk<T, MODE>(a.A.f0, a.A.f1, (int64_t)6 * n + q, xval<T, MODE>(a, a.fcell[q]), y0, y1);
+        int p = a.fperf[q];
+        if (p >= 0) acc_blk<T, MODE>(a.A.fw0, a.A.fw1, p, xval<T, MODE>(a, 2 * n + a.perf_well[p]), y0, y1);
+        sp_store<T, MODE>(a, row, y0, y1, xs);
+    } else {
+        int w = b - bm - bf;
+        int row = 2 * n + w;
+        T y0 = 0, y1 = 0;
+        for (int p = a.well_ptr[w] + threadIdx.x; p < a.well_ptr[w + 1]; p += blockDim.x)
+            acc_blk<T, MODE>(a.A.wf0, a.A.wf1, p, xval<T, MODE>(a, n + a.perf_q[p]), y0, y1);
+        y0 = wave_sum(y0);
+        y1 = wave_sum(y1);
+        if (threadIdx.x % WAVE == 0) {
+            sh0[threadIdx.x / WAVE] = y0;
+            sh1[threadIdx.x / WAVE] = y1;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            T s0 = 0, s1 = 0;
+            for (int i = 0; i < (int)(blockDim.x / WAVE); ++i) {
+                s0 += sh0[i];
+                s1 += sh1[i];
+            }
+            V2<T> xs = xval<T, MODE>(a, row);
+            acc_blk<T, MODE>(a.A.d0, a.A.d1, row, xs, s0, s1);
+            sp_store<T, MODE>(a, row, s0, s1, xs);
+        }
+    }
+}
+
+template <class T>
+static SpArgs<T> sp_args(dp_sim* s, const BMat<T>& A) {
+    Topo& t = s->topo;
+    SpArgs<T> a{};
+    a.A = A;
+    a.fcol = t.fcol;
+    a.fcell = t.fcell;
+    a.frow = t.frow;
+    a.fperf = t.fperf;
+    a.perf_q = t.perf_q;
+    a.perf_well = t.perf_well;
+    a.well_ptr = t.well_ptr;
+    a.n = t.n;
+    a.nw = t.nw;
+    return a;
+}
+
+template <class T, int MODE>
+static void sp_launch(dp_sim* s, const SpArgs<T>& a) {
+    int bm = ceil_div(s->topo.n, 256);
+    spmv_kernel<T, MODE><<<2 * bm + s->topo.nw, 256, 0, s->stream>>>(a, bm, bm);
+    DP_LAUNCH_CHECK();
+}
+
+template <class T>
+const BMat<T>& amat(dp_sim* s);
+template <>
+const BMat<double>& amat<double>(dp_sim* s) { return s->A; }
+template <>
+const BMat<float>& amat<float>(dp_sim* s) { return s->A32; }
+
+template <class T>
+void bspmv(dp_sim* s, const V2<T>* x, V2<T>* y) {
+    SpArgs<T> a = sp_args<T>(s, amat<T>(s));
+    a.x = x;
+    a.y = y;
+    sp_launch<T, MODE_Y>(s, a);
+}
+template <class T>
+void bresidual(dp_sim* s, const V2<T>* b, const V2<T>* x, V2<T>* y) {
+    SpArgs<T> a = sp_args<T>(s, amat<T>(s));
+    a.x = x;
+    a.b = b;
+    a.y = y;
+    sp_launch<T, MODE_RES>(s, a);
+}
+template <class T>
+void bresidual_p(dp_sim* s, const V2<T>* b, const V2<T>* x, T* yp) {
+    SpArgs<T> a = sp_args<T>(s, amat<T>(s));
+    a.x = x;
+    a.b = b;
+    a.yp = yp;
+    sp_launch<T, MODE_RESP>(s, a);
+}
+template <class T>
+void bresidual_prol(dp_sim* s, const V2<T>* b, const V2<T>* x, const T* e, V2<T>* x2, V2<T>* y) {
+    SpArgs<T> a = sp_args<T>(s, amat<T>(s));
+    a.x = x;
+    a.b = b;
+    a.e = e;
+    a.x2 = x2;
+    a.y = y;
+    sp_launch<T, MODE_PROL>(s, a);
+}
+
+template void bspmv<double>(dp_sim*, const d2*, d2*);
+template void bspmv<float>(dp_sim*, const f2*, f2*);
+template void bresidual<double>(dp_sim*, const d2*, const d2*, d2*);
+template void bresidual<float>(dp_sim*, const f2*, const f2*, f2*);
+template void bresidual_p<double>(dp_sim*, const d2*, const d2*, double*);
+template void bresidual_p<float>(dp_sim*, const f2*, const f2*, float*);
+template void bresidual_prol<double>(dp_sim*, const d2*, const d2*, const double*, d2*, d2*);
+template void bresidual_prol<float>(dp_sim*, const f2*, const f2*, const float*, f2*, f2*);
+
+// ---------------------------------------------------------------------------
+// Block ILU(0) factorisation in the elimination order (matrix nodes, even
+// fracture nodes, odd fracture nodes, wells).  The matrix node of a cell couples
+// only to its fracture node, so its elimination is exact; even fracture rows
+// couple only to odd ones, so their rows see only the matrix-node update; odd
+// rows take updates from their matrix node and from every even neighbour; a
+// well row takes updates from all its perforated rows, even ones first.
+// ---------------------------------------------------------------------------
+template <class T>
+struct IluArgs {
+    BMat<T> A;
+    ILUF<T> F;
+    const int* fcol;
+    const unsigned char* fmask;
+    const int* fcell;
+    const int* fperf;
+    const int* perf_q;
+    const int* perf_well;
+    const int* well_ptr;
+    int n, nw, nred;
+};
+
+// even (red) rows: L_rm = A_rm U_mm^-1, U_rr = A_rr - L_rm A_mr
+template <class T>
+__global__ void ilu_red_kernel(IluArgs<T> a) {
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= a.nred) return;
+    int n = a.n;
+    int c = a.fcell[q];
+    Blk<T> um_inv = binv(ldb(a.A.d0, a.A.d1, c));
+    stb(a.F.ui0, a.F.ui1, c, um_inv);
+    Blk<T> l = bmm(ldb(a.A.f0, a.A.f1, (int64_t)6 * n + q), um_inv);
+    stb(a.F.l0, a.F.l1, (int64_t)6 * n + q, l);
+    Blk<T> d = bsub(ldb(a.A.d0, a.A.d1, n + q), bmm(l, ldb(a.A.m0, a.A.m1, c)));
+    stb(a.F.ui0, a.F.ui1, n + q, binv(d));
+    int p = a.fperf[q];
+    if (p >= 0) stb(a.F.ubw0, a.F.ubw1, p, ldb(a.A.fw0, a.A.fw1, p));
+}
+
+// odd (black) rows
+template <class T>
+__global__ void ilu_black_kernel(IluArgs<T> a) {
+    int q = a.nred + blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= a.n) return;
+    int n = a.n;
+    int c = a.fcell[q];
+    Blk<T> um_inv = binv(ldb(a.A.d0, a.A.d1, c));
+    stb(a.F.ui0, a.F.ui1, c, um_inv);
+    Blk<T> l6 = bmm(ldb(a.A.f0, a.A.f1, (int64_t)6 * n + q), um_inv);
+    stb(a.F.l0, a.F.l1, (int64_t)6 * n + q, l6);
+    Blk<T> d = bsub(ldb(a.A.d0, a.A.d1, n + q), bmm(l6, ldb(a.A.m0, a.A.m1, c)));
+    int p = a.fperf[q];
+    int w = p >= 0 ? a.perf_well[p] : -1;
+    Blk<T> ubw = {0, 0, 0, 0};
+    if (p >= 0) ubw = ldb(a.A.fw0, a.A.fw1, p);
+    unsigned mask = a.fmask[q];
+    for (int s = 0; s < 6; ++s) {
+        Blk<T> l = {0, 0, 0, 0};
+        if (mask & (1u << s)) {
+            int rpos = a.fcol[s * n + q];
+            int rq = rpos - n;
+            l = bmm(ldb(a.A.f0, a.A.f1, (int64_t)s * n + q), ldb(a.F.ui0, a.F.ui1, rpos));
+            // the even row's block pointing back at this row sits in the opposite slot
+            d = bsub(d, bmm(l, ldb(a.A.f0, a.A.f1, (int64_t)(s ^ 1) * n + rq)));
+            int pr = a.fperf[rq];
+            if (w >= 0 && pr >= 0 && a.perf_well[pr] == w) ubw = bsub(ubw, bmm(l, ldb(a.A.fw0, a.A.fw1, pr)));
+        }
+        stb(a.F.l0, a.F.l1, (int64_t)s * n + q, l);
+    }
+    stb(a.F.ui0, a.F.ui1, n + q, binv(d));
+    if (p >= 0) stb(a.F.ubw0, a.F.ubw1, p, ubw);
+}
+
+// well rows: one thread per well, perforations in elimination order
+template <class T>
+__global__ void ilu_well_kernel(IluArgs<T> a) {
+    int w = blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= a.nw) return;
+    int n = a.n;
+    int p0 = a.well_ptr[w], p1 = a.well_ptr[w + 1];
+    for (int p = p0; p < p1; ++p) stb(a.F.lw0, a.F.lw1, p, ldb(a.A.wf0, a.A.wf1, p));
+    Blk<T> dw = ldb(a.A.d0, a.A.d1, 2 * n + w);
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int p = p0; p < p1; ++p) {
+            int q = a.perf_q[p];
+            bool red = q < a.nred;
+            if (red != (pass == 0)) continue;
+            Blk<T> l = bmm(ldb(a.F.lw0, a.F.lw1, p), ldb(a.F.ui0, a.F.ui1, n + q));
+            stb(a.F.lw0, a.F.lw1, p, l);
+            if (red) {
+                unsigned mask = a.fmask[q];
+                for (int s = 0; s < 6; ++s) {
+                    if (!(mask & (1u << s))) continue;
+                    int bq = a.fcol[s * n + q] - n;
+                    int pb = a.fperf[bq];
+                    if (pb >= 0 && a.perf_well[pb] == w) {
+                        Blk<T> u = ldb(a.A.f0, a.A.f1, (int64_t)s * n + q);
+                        stb(a.F.lw0, a.F.lw1, pb, bsub(ldb(a.F.lw0, a.F.lw1, pb), bmm(l, u)));
+                    }
+                }
+            }
+            dw = bsub(dw, bmm(l, ldb(a.F.ubw0, a.F.ubw1, p)));
+        }
+    }
+    stb(a.F.ui0, a.F.ui1, 2 * n + w, binv(dw));
+}
+
+template <class T>
+const ILUF<T>& ilu_of(dp_sim* s);
+template <>
+const ILUF<double>& ilu_of<double>(dp_sim* s) { return s->ilu64; }
+template <>
+const ILUF<float>& ilu_of<float>(dp_sim* s) { return s->ilu32; }
+
+template <class T>
+static IluArgs<T> ilu_args(dp_sim* s) {
+    Topo& t = s->topo;
+    IluArgs<T> a;
+    a.A = amat<T>(s);
+    a.F = ilu_of<T>(s);
+    a.fcol = t.fcol;
+    a.fmask = t.fmask;
+    a.fcell = t.fcell;
+    a.fperf = t.fperf;
+    a.perf_q = t.perf_q;
+    a.perf_well = t.perf_well;
+    a.well_ptr = t.well_ptr;
+    a.n = t.n;
+    a.nw = t.nw;
+    a.nred = t.nred;
+    return a;
+}
+
+template <class T>
+void ilu_factor(dp_sim* s) {
+    Topo& t = s->topo;
+    IluArgs<T> a = ilu_args<T>(s);
+    if (t.nred > 0) ilu_red_kernel<T><<<ceil_div(t.nred, 256), 256, 0, s->stream>>>(a);
+    DP_LAUNCH_CHECK();
+    if (t.n - t.nred > 0) ilu_black_kernel<T><<<ceil_div(t.n - t.nred, 256), 256, 0, s->stream>>>(a);
+    DP_LAUNCH_CHECK();
+    if (t.nw > 0) ilu_well_kernel<T><<<ceil_div(t.nw, 64), 64, 0, s->stream>>>(a);
+    DP_LAUNCH_CHECK();
+}
+template void ilu_factor<double>(dp_sim*);
+template void ilu_factor<float>(dp_sim*);
+
+// ---------------------------------------------------------------------------
+// Block ILU(0) solve z = (LU)^-1 r.  y and z share the output array.
+//   even rows:  y_r = r_r - L_rm r_m
+//   odd rows:   y_b = r_b - L_bm r_m - sum_s L_bs y_rs; without a perforation
+//               z_b = U_bb^-1 y_b and z_m = U_mm^-1 (r_m - A_mb z_b) at once
+//   wells:      y_w = r_w - sum_p L_wp y_p; z_w = U_ww^-1 y_w; then the
+//               perforated odd rows and their matrix nodes
+//   even rows:  z_r = U_rr^-1 (y_r - sum_s A_rs z_bs - A_rw z_w), then z_m
+// ---------------------------------------------------------------------------
+template <class T>
+struct IluSolveArgs {
+    IluArgs<T> f;
+    const V2<T>* r;
+    V2<T>* z;
+};
+
+template <class T>
+__global__ void ilus_red_fwd(IluSolveArgs<T> a) {
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= a.f.nred) return;
+    int n = a.f.n;
+    int c = a.f.fcell[q];
+    V2<T> y = vsub(a.r[n + q], bmv(ldb(a.f.F.l0, a.f.F.l1, (int64_t)6 * n + q), a.r[c]));
+    a.z[n + q] = y;
+}
+
+template <class T>
+__global__ void ilus_black(IluSolveArgs<T> a) {
+    int q = a.f.nred + blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= a.f.n) return;
+    int n = a.f.n;
+    int c = a.f.fcell[q];
+    V2<T> rm = a.r[c];
+    V2<T> y = vsub(a.r[n + q], bmv(ldb(a.f.F.l0, a.f.F.l1, (int64_t)6 * n + q), rm));
+    unsigned mask = a.f.fmask[q];
+#pragma unroll
+    for (int s = 0; s < 6; ++s)
+        if (mask & (1u << s))
+            y = vsub(y, bmv(ldb(a.f.F.l0, a.f.F.l1, (int64_t)s * n + q), a.z[a.f.fcol[s * n + q]]));
+    if (a.f.fperf[q] >= 0) {
+        a.z[n + q] = y;
+        return;
+    }
+    V2<T> zb = bmv(ldb(a.f.F.ui0, a.f.F.ui1, n + q), y);
+    a.z[n + q] = zb;
+    a.z[c] = bmv(ldb(a.f.F.ui0, a.f.F.ui1, c), vsub(rm, bmv(ldb(a.f.A.m0, a.f.A.m1, c), zb)));
+}
+
+template <class T>
+__global__ void ilus_well(IluSolveArgs<T> a) {
+    __shared__ T sh0[256 / WAVE], sh1[256 / WAVE];
+    __shared__ V2<T> zw_sh;
+    int w = blockIdx.x;
+    int n = a.f.n;
+    int p0 = a.f.well_ptr[w], p1 = a.f.well_ptr[w + 1];
+    T y0 = 0, y1 = 0;
+    for (int p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+        V2<T> v = bmv(ldb(a.f.F.lw0, a.f.F.lw1, p), a.z[n + a.f.perf_q[p]]);
+        y0 += v.x;
+        y1 += v.y;
+    }
+    y0 = wave_sum(y0);
+    y1 = wave_sum(y1);
+    if (threadIdx.x % WAVE == 0) {
+        sh0[threadIdx.x / WAVE] = y0;
+        sh1[threadIdx.x / WAVE] = y1;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        T s0 = 0, s1 = 0;
+        for (int i = 0; i < (int)(blockDim.x / WAVE); ++i) {
+            s0 += sh0[i];
+            s1 += sh1[i];
+        }
+        V2<T> rw = a.r[2 * n + w];
+        V2<T> zw = bmv(ldb(a.f.F.ui0, a.f.F.ui1, 2 * n + w), mk2<T>(rw.x - s0, rw.y - s1));
+        a.z[2 * n + w] = zw;
+        zw_sh = zw;
+    }
+    __syncthreads();
+    V2<T> zw = zw_sh;
+    for (int p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+        int q = a.f.perf_q[p];
+        if (q < a.f.nred) continue;
+        int c = a.f.fcell[q];
+        V2<T> y = vsub(a.z[n + q], bmv(ldb(a.f.F.ubw0, a.f.F.ubw1, p), zw));
+        V2<T> zb = bmv(ldb(a.f.F.ui0, a.f.F.ui1, n + q), y);
+        a.z[n + q] = zb;
+        a.z[c] = bmv(ldb(a.f.F.ui0, a.f.F.ui1, c), vsub(a.r[c], bmv(ldb(a.f.A.m0, a.f.A.m1, c), zb)));
+    }
+}
+
+template <class T>
+__global__ void ilus_red_bwd(IluSolveArgs<T> a) {
+    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= a.f.nred) return;
+    int n = a.f.n;
+    int c = a.f.fcell[q];
+    V2<T> y = a.z[n + q];
+    unsigned mask = a.f.fmask[q];
+#pragma unroll
+    for (int s = 0; s < 6; ++s)
+        if (mask & (1u << s))
+            y = vsub(y, bmv(ldb(a.f.A.f0, a.f.A.f1, (int64_t)s * n + q), a.z[a.f.fcol[s * n + q]]));
+    int p = a.f.fperf[q];
+    if (p >= 0) y = vsub(y, bmv(ldb(a.f.F.ubw0, a.f.F.ubw1, p), a.z[2 * n + a.f.perf_well[p]]));
+    V2<T> zr = bmv(ldb(a.f.F.ui0, a.f.F.ui1, n + q), y);
+    a.z[n + q] = zr;
+    a.z[c] = bmv(ldb(a.f.F.ui0, a.f.F.ui1, c), vsub(a.r[c], bmv(ldb(a.f.A.m0, a.f.A.m1, c), zr)));
+}
+
+template <class T>
+void ilu_solve(dp_sim* s, const V2<T>* r, V2<T>* z) {
+    Topo& t = s->topo;
+    IluSolveArgs<T> a{ilu_args<T>(s), r, z};
+    int nb_red = ceil_div(t.nred, 256), nb_black = ceil_div(t.n - t.nred, 256);
+    if (nb_red) ilus_red_fwd<T><<<nb_red, 256, 0, s->stream>>>(a);
+    if (nb_black) ilus_black<T><<<nb_black, 256, 0, s->stream>>>(a);
+    if (t.nw) ilus_well<T><<<t.nw, 256, 0, s->stream>>>(a);
+    if (nb_red) ilus_red_bwd<T><<<nb_red, 256, 0, s->stream>>>(a);
+    DP_LAUNCH_CHECK();
+}
+template void ilu_solve<double>(dp_sim*, const d2*, d2*);
+template void ilu_solve<float>(dp_sim*, const f2*, f2*);
+
+}  // namespace dp
