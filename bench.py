@@ -1,0 +1,216 @@
+"""Benchmark: linear solves per second at 4.49M DOF on one MI355X.
+
+One step = one linear solve of an inexact-Newton iteration on the 60x220x85
+channelised dual-porosity model: residual/Jacobian assembly, CPR-FPF setup
+(decoupling, block ILU(0), pressure AMG) and GMRES(30) to a relative residual
+of 1e-6.  The Jacobian is the first Newton iterate of the step after two
+10-day timesteps, and it is re-assembled and set up from scratch in every
+step.  The headline value uses the FP32 preconditioner under the FP64 Krylov
+loop; the plain FP64 form is measured in the same run.
+
+Prints one JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# kernel group reported in the roofline object (the other groups are listed too)
+ROOFLINE_KERNEL = "block_ilu0_solve"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_model(nz):
+    import synth
+
+    return synth.config2(nz=nz, steps=20)
+
+
+def slab(model, nz):
+    """The top nz layers of a model (fields cut, wells cut to the slab)."""
+    import copy
+
+    m = copy.deepcopy(model)
+    n = m["nx"] * m["ny"] * nz
+    for k in ("kx", "ky", "kz", "km", "phi_f", "phi_m"):
+        m[k] = m[k][:n].copy()
+    m["p0"] = m["p0"][:2 * n].copy()
+    m["sw0"] = m["sw0"][:2 * n].copy()
+    m["nz"] = nz
+    for w in m["wells"]:
+        w["k1"] = min(w["k1"], nz - 1)
+    return m
+
+
+def prepare(sim, model, warm_steps):
+    """Advance warm_steps timesteps, then start a step: returns dt."""
+    dt = model["schedule"][0]
+    for _ in range(warm_steps):
+        sim.timestep(dt)
+    sim.mark_old()
+    return dt
+
+
+def one_solve(sim, dt, rtol):
+    sim.assemble(dt)
+    sim.setup()
+    its, rel = sim.solve(rtol, 300, allow_noconv=True)
+    return its, rel
+
+
+def timed_form(model, precision, steps, warmup, rtol, state=None):
+    import torch
+
+    from paper_1808_04338_amd import Sim
+
+    sim = Sim(model, precision=precision, lin_rtol=rtol)
+    if state is None:
+        dt = prepare(sim, model, 2)
+        state = sim.get_state()
+    else:
+        sim.set_state(*state)
+        sim.mark_old()
+        dt = model["schedule"][0]
+    # the start-of-step accumulation of the warm state
+    for _ in range(warmup):
+        one_solve(sim, dt, rtol)
+    torch.cuda.synchronize()
+    lat = []
+    its_l = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        a = time.perf_counter()
+        its, rel = one_solve(sim, dt, rtol)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - a)
+        its_l.append(its)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    # per-phase device times of one more step
+    sim.enable_timing(True)
+    one_solve(sim, dt, rtol)
+    phases = {name: sim.phase_time(i)[0] for i, name in enumerate(
+        ["assembly_ms", "setup_ms", "solve_ms", "spmv_ms_total", "precond_ms_total"])}
+    sim.enable_timing(False)
+    kern = sim.bench_kernels(20)
+    levels = sim.amg_info()
+    out = dict(wall=wall, lat=lat, iters=its_l, rel=rel, phases=phases, kern=kern,
+               amg_rows=[int(r) for r in levels[1]], amg_nnz=[int(r) for r in levels[2]],
+               footprint=sim.footprint, n_dof=sim.n_dof, nnz=sim.nnz)
+    sim.close()
+    return out, state
+
+
+def cpu_baseline(model, rtol, nz_sample):
+    """The oracle's CPR-FPF (textbook, NumPy/SciPy) on the top nz_sample layers
+    of the same model at its initial state: assembly + setup + GMRES."""
+    from oracle import cpr as ocpr
+    from oracle import physics as oph
+
+    m = slab(model, nz_sample)
+    geo = oph.Geometry(m)
+    ctrl = [w["control"] for w in m["wells"]]
+    x = oph.initial_state(m)
+    acc = oph.accumulation(geo, x)
+    dt = m["schedule"][0]
+    t0 = time.perf_counter()
+    R = oph.residual(geo, x, acc, dt, ctrl)
+    J = oph.jacobian(geo, x, dt, ctrl)
+    _, its, rel = ocpr.solve(geo, J, -R, rtol=rtol)
+    t = time.perf_counter() - t0
+    return t, geo.N, its
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--rtol", type=float, default=1e-6)
+    ap.add_argument("--nz", type=int, default=85)
+    ap.add_argument("--cpu-layers", type=int, default=6)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(see DESIGN.md for how the solve would shard)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    log("generating the 60x220x%d model" % args.nz)
+    model = make_model(args.nz)
+    log("FP32-preconditioner form")
+    r32, state = timed_form(model, "fp32", args.steps, args.warmup, args.rtol)
+    r64 = None
+    if not args.no_fp64:
+        log("FP64 form")
+        r64, _ = timed_form(model, "fp64", args.steps, args.warmup, args.rtol, state=state)
+    ms = 1000.0 * r32["wall"] / args.steps
+    value = args.steps / r32["wall"]
+    lat = np.array(r32["lat"]) * 1000.0
+    kern = {k["name"]: k for k in r32["kern"]}
+    k = kern[ROOFLINE_KERNEL]
+    roof = dict(bound="hbm", kernel=k["name"], achieved=k["bytes"] / (k["ms"] * 1e-3) / 1e9,
+                peak=HBM_PEAK_GBS, unit="GB/s", traffic=None, bytes_per_launch=k["bytes"],
+                avg_ms=k["ms"])
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    cpu = None
+    if not args.no_cpu:
+        log("oracle CPU baseline on a %d-layer slab" % args.cpu_layers)
+        t, ndof, its = cpu_baseline(model, args.rtol, args.cpu_layers)
+        full = r32["n_dof"]
+        cpu = dict(value=(1.0 / t) * (ndof / full), unit="solves/s", cores=1, kind="oracle",
+                   sample="assembly + CPR-FPF setup + GMRES(30) to %g on the top %d layers "
+                          "(%d DOF) at the initial state, %.1f s, %d iterations; rate scaled by "
+                          "DOF to the full 4.49M-DOF model" % (args.rtol, args.cpu_layers, ndof, t, its))
+    out = {
+        "metric": "linear solves/s at 4.5M DOF, FP32-precond vs FP64 to 1e-6 rtol; p50/p99 latency",
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64 Krylov + f32 preconditioner",
+        "data": "synthetic",
+        "config": {"workload": "dual-porosity oil-water 60x%dx%d channelised, %d DOF, assembly + "
+                               "CPR-FPF setup + GMRES(30) to rtol %g, FP32 preconditioner"
+                               % (220, args.nz, r32["n_dof"], args.rtol),
+                   "dof": r32["n_dof"], "nnz": r32["nnz"]},
+        "p50_ms": float(np.percentile(lat, 50)),
+        "p99_ms": float(np.percentile(lat, 99)),
+        "gmres_iters": r32["iters"],
+        "phases_ms": r32["phases"],
+        "amg_rows": r32["amg_rows"],
+        "roofline": roof,
+        "kernels": r32["kern"],
+        "cpu_baseline": cpu,
+    }
+    if r64 is not None:
+        lat64 = np.array(r64["lat"]) * 1000.0
+        out["fp64"] = {"value": args.steps / r64["wall"], "unit": "solves/s",
+                       "ms_per_step": 1000.0 * r64["wall"] / args.steps,
+                       "p50_ms": float(np.percentile(lat64, 50)),
+                       "p99_ms": float(np.percentile(lat64, 99)),
+                       "gmres_iters": r64["iters"], "phases_ms": r64["phases"],
+                       "kernel": r64["kern"]}
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -95,7 +95,7 @@ typedef struct {
     int32_t amg_coarse_max;   /* [2000], at most 4096 */
     int32_t amg_max_levels;   /* [25] */
     double amg_theta;         /* [0.25] */
-    int32_t amg_trunc;        /* [4], at most 8 */
+    int32_t amg_trunc;        /* interpolation entries kept per row [3], at most 8 */
     double newton_tol;        /* scaled max-norm of the residual [1e-8] */
     int32_t max_newton;       /* [20] */
     int32_t max_cuts;         /* [8] */
@@ -198,9 +198,11 @@ dp_status sim_export_ilu(dp_sim *sim, int32_t *perm, int32_t *brow, int32_t *bco
 dp_status sim_amg_info(dp_sim *sim, int32_t *levels, int32_t *rows, int64_t *nnz);
 
 /* Level l: splitting cf[rows[l]] (1 = C, -1 = F; not for the coarsest), the
- * operator A_l in CSR (level-0 rows in elimination-position order), and for
- * l < levels-1 the interpolation P_l in CSR.  Pass NULL to skip an output.
- * p_nnz returns nnz(P_l). */
+ * operator A_l in CSR, and for l < levels-1 the interpolation P_l in CSR.
+ * Level 0 is the pressure system with the matrix-node pressures eliminated
+ * exactly: its rows are the fracture nodes in elimination order (even cells,
+ * then odd cells, each by cell index), then the wells.  Pass NULL to skip an
+ * output.  p_nnz returns nnz(P_l). */
 dp_status sim_export_amg_level(dp_sim *sim, int32_t level, int32_t *cf, int32_t *a_rowptr,
                                int32_t *a_col, double *a_val, int32_t *p_rowptr, int32_t *p_col,
                                double *p_val, int64_t *p_nnz);
@@ -212,7 +214,7 @@ dp_status sim_apply_matrix(dp_sim *sim, const double *x, double *y);
 
 /* One stage of the preconditioner on host vectors.  stage 0: z = (LU)^-1 r,
  * block ILU(0) [n_dof, canonical order].  stage 1: z = V-cycle(r) on the
- * level-0 pressure system [rows[0], elimination-position order]. */
+ * level-0 pressure system [rows[0], the order of sim_export_amg_level]. */
 dp_status sim_apply_stage(dp_sim *sim, int32_t stage, const double *r, double *z);
 
 /* Self-test of the dense coarse-level inverse (blocked Gauss-Jordan with MFMA
@@ -221,6 +223,15 @@ dp_status sim_apply_stage(dp_sim *sim, int32_t stage, const double *r, double *z
  * rounded up to 32) and stream. */
 dp_status dp_selftest_dense_inverse(const double *a, int32_t n, double *ainv, void *d_workspace,
                                     size_t workspace_bytes, void *hip_stream);
+
+/* Time one kernel group on the handle's stream with HIP events, reps launches
+ * after one untimed launch; returns the average ms per launch and the
+ * algorithmic bytes one launch must move (values and indices read once, vectors
+ * read and written once).  kernel 0: FP64 block SpMV of the decoupled matrix;
+ * 1: block ILU(0) solve (preconditioner precision); 2: AMG V-cycle; 3:
+ * residual/Jacobian assembly; 4: whole CPR-FPF apply.  After cpr_fpf_setup. */
+dp_status sim_bench_kernel(dp_sim *sim, int32_t kernel, int32_t reps, double *avg_ms,
+                           double *bytes);
 
 /* Average device time (ms) of the named phase over the calls since the last
  * reset: 0 assembly, 1 setup, 2 solve, 3 SpMV, 4 preconditioner apply.

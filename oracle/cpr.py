@@ -16,11 +16,18 @@ Readings of what the paper leaves open:
 * Block ILU(0) takes the elimination ordering as an argument.  The ordering
   used throughout is: all matrix nodes, then fracture nodes with i+j+k even,
   then those with i+j+k odd, then wells.
-* Classical AMG: strength theta = 0.25 on -a_ij sign(a_ii); PMIS coarsening
-  with weights |S^T_i| + h(i)/2^32, h = lowbias32; distance-two ("extended")
-  interpolation written as W = -D^-1 (A^s_FC + A^s_FF B^-1 Abar^s_FC),
-  truncated to 4 entries per row (row sum kept); Galerkin coarse operators
-  R A P with R = P^T; l1-Jacobi smoothing; coarsest level solved exactly.
+* Pressure stage: the pressure system is taken in the elimination order.  A
+  matrix-node pressure couples only to the pressure of its own fracture node,
+  so it is eliminated exactly first (a diagonal Schur complement on the
+  fracture and well pressures; the matrix pressures are recovered afterwards).
+  This is the ideal first coarsening of the pressure system (C = fracture and
+  well unknowns, F = matrix nodes).
+* Classical AMG on the reduced system: strength theta = 0.25 on
+  -a_ij sign(a_ii); PMIS coarsening with weights |S^T_i| + h(i)/2^32,
+  h = lowbias32; distance-two ("extended") interpolation written as
+  W = -D^-1 (A^s_FC + A^s_FF B^-1 Abar^s_FC), truncated to 3 entries per row
+  (row sum kept); Galerkin coarse operators R A P with R = P^T; l1-Jacobi
+  smoothing; coarsest level solved exactly.
 * GMRES: right-preconditioned, restart 30, classical Gram-Schmidt with one
   re-orthogonalisation pass, Givens rotations; the tolerance is on the
   decoupled residual.
@@ -301,10 +308,32 @@ def l1_diag(A):
     return diag + sgn * s
 
 
-class AMG:
-    """Classical AMG hierarchy on the pressure matrix."""
+def reduced_pressure_matrix(App, n):
+    """Exact elimination of the first n unknowns of App (matrix-node pressures,
+    each coupled only to its own fracture pressure): the Schur complement
+    App[n:, n:] - App[n:, :n] D^-1 App[:n, n:] with D = diag(App[:n, :n]).  Only
+    the diagonal of App[n:, n:] changes, so its stored pattern is kept."""
+    App = App.tocsr()
+    D = App[:n, :n].diagonal()
+    S = App[n:, n:].tocsr().copy()
+    S.sort_indices()
+    upd = (App[n:, :n] @ sp.diags(1.0 / D) @ App[:n, n:]).tocsr()
+    if upd.nnz:
+        rows = np.repeat(np.arange(upd.shape[0]), np.diff(upd.indptr))
+        if not np.all(upd.indices == rows):
+            raise ValueError("matrix nodes must couple to one fracture node only")
+        dpos = np.empty(S.shape[0], dtype=np.int64)
+        srows = np.repeat(np.arange(S.shape[0]), np.diff(S.indptr))
+        dmask = S.indices == srows
+        dpos[srows[dmask]] = np.nonzero(dmask)[0]
+        S.data[dpos[rows]] -= upd.data
+    return S, D
 
-    def __init__(self, A, theta=0.25, max_coarse=2000, max_levels=25, trunc=4):
+
+class AMG:
+    """Classical AMG hierarchy on a pressure matrix."""
+
+    def __init__(self, A, theta=0.25, max_coarse=2000, max_levels=25, trunc=3):
         self.levels = []
         A = A.tocsr()
         while True:
@@ -357,13 +386,29 @@ class CPRFPF:
             self.ilu = BlockILU0(indptr, indices, data, self.perm)
             self.fsolve = self.ilu.solve
         self.Ap = pressure_matrix(indptr, indices, data)
-        self.amg = AMG(self.Ap, **(amg_opts or {}))
+        self.n = geo.n
+        self.App = self.Ap[self.perm][:, self.perm].tocsr()
+        self.S, self.D = reduced_pressure_matrix(self.App, self.n)
+        self.amg = AMG(self.S, **(amg_opts or {}))
         self.nb = nb
+
+    def pressure_solve(self, rp):
+        """Approximate A_p^-1 rp: exact matrix-node elimination, one V-cycle on
+        the reduced system, back-substitution.  rp in canonical block order."""
+        n = self.n
+        q = rp[self.perm]
+        rm, rf = q[:n], q[n:]
+        rr = rf - self.App[n:, :n] @ (rm / self.D)
+        ef = self.amg.vcycle(rr)
+        em = (rm - self.App[:n, n:] @ ef) / self.D
+        e = np.empty_like(rp)
+        e[self.perm] = np.concatenate([em, ef])
+        return e
 
     def apply(self, r):
         z = self.fsolve(r)
         res = r - self.A @ z
-        e = self.amg.vcycle(res[0::2])
+        e = self.pressure_solve(res[0::2])
         z = z.copy()
         z[0::2] += e
         res = r - self.A @ z

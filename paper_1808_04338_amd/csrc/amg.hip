@@ -6,6 +6,7 @@
 //
 // Setup runs in FP64; the apply copies (SELL-64 operators, l1 diagonals, dense
 // coarse inverse) are kept in the preconditioner precision.
+#include <algorithm>
 #include <cstdlib>
 #include <vector>
 
@@ -19,25 +20,31 @@ constexpr int ST_U = 0;
 constexpr int ST_F = -1;
 
 // ---------------------------------------------------------------------------
-// Level-0 pressure matrix: entry (0,0) of each block of the decoupled matrix
+// Level-0 pressure matrix: entry (0,0) of each block of the decoupled matrix,
+// with the matrix-node pressures eliminated exactly.  A matrix node couples
+// only to its own fracture node, so the Schur complement changes only the
+// fracture diagonal: a_ff - a_fm (1/a_mm) a_mf.
 // ---------------------------------------------------------------------------
 __global__ void extract_ap_kernel(BMat<double> A, const int* __restrict__ rowptr,
-                                  const int* __restrict__ src, const int* __restrict__ fperf, int n,
-                                  int nb, double* val) {
+                                  const int* __restrict__ src, const int* __restrict__ fperf,
+                                  const int* __restrict__ fcell, int n, int nr, double* val) {
     int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nb) return;
+    if (r >= nr) return;
     for (int e = rowptr[r]; e < rowptr[r + 1]; ++e) {
         int code = src[e];
         double v;
         if (r < n) {
-            v = code == 0 ? A.d0[r].x : A.m0[r].x;
-        } else if (r < 2 * n) {
-            int q = r - n;
-            if (code < 7) v = A.f0[(int64_t)code * n + q].x;
-            else if (code == 7) v = A.d0[r].x;
-            else v = A.fw0[fperf[q]].x;
+            int q = r;
+            if (code < 6) {
+                v = A.f0[(int64_t)code * n + q].x;
+            } else if (code == 7) {
+                int c = fcell[q];
+                v = A.d0[n + q].x - A.f0[(int64_t)6 * n + q].x * (1.0 / A.d0[c].x) * A.m0[c].x;
+            } else {
+                v = A.fw0[fperf[q]].x;
+            }
         } else {
-            v = code < 0 ? A.d0[r].x : A.wf0[code].x;
+            v = code < 0 ? A.d0[n + r].x : A.wf0[code].x;
         }
         val[e] = v;
     }
@@ -45,8 +52,9 @@ __global__ void extract_ap_kernel(BMat<double> A, const int* __restrict__ rowptr
 
 void amg_extract_level0(dp_sim* s) {
     Topo& t = s->topo;
-    extract_ap_kernel<<<ceil_div(t.nb, 256), 256, 0, s->stream>>>(s->A, s->Ap0.rowptr, s->ap_src,
-                                                                 t.fperf, t.n, t.nb, s->Ap0.val);
+    int nr = t.n + t.nw;
+    extract_ap_kernel<<<ceil_div(nr, 256), 256, 0, s->stream>>>(s->A, s->Ap0.rowptr, s->ap_src, t.fperf,
+                                                               t.fcell, t.n, nr, s->Ap0.val);
     DP_LAUNCH_CHECK();
 }
 
@@ -649,35 +657,70 @@ __global__ void copy_inv(const double* __restrict__ M, int np, int n, T* out) {
 // ---------------------------------------------------------------------------
 // Setup driver
 // ---------------------------------------------------------------------------
-static void build_sell(dp_sim* s, const Csr& A, Sell& S, bool pad_self, Arena& H, Arena& Sc,
-                       const char* what) {
+template <class T>
+__global__ void cast_vals(const double* __restrict__ a, int64_t n, T* b) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (T)a[i];
+}
+
+// Choose and build the apply form of a CSR operator.  SELL-64 when it pads by
+// at most 30% and no row is longer than 48, otherwise CSR with G lanes per row
+// (G the power of two at or above the mean row length, 4..64).
+static void build_op(dp_sim* s, const Csr& A, Op& op, bool pad_self, Arena& H, Arena& Sc,
+                     const char* what) {
     hipStream_t st = s->stream;
-    S.n = A.n;
-    S.nslices = (A.n + 63) / 64;
-    S.sptr = H.get<int>(S.nslices + 1, what);
+    op.n = A.n;
+    op.nnz = A.nnz;
+    int nsl = (A.n + 63) / 64;
     size_t mark = Sc.top;
-    int64_t* w = Sc.get<int64_t>(S.nslices + 1, "sell widths");
-    int64_t* tmp = Sc.get<int64_t>(scan_tmp_size(S.nslices + 1), "sell scan");
+    int64_t* w = Sc.get<int64_t>(nsl + 1, "sell widths");
+    int64_t* tmp = Sc.get<int64_t>(scan_tmp_size(nsl + 1), "sell scan");
     int64_t total = 0;
-    if (S.nslices > 0) {
-        sell_width<<<ceil_div(S.nslices, 256), 256, 0, st>>>(A, S.nslices, w);
+    int64_t maxw = 0;
+    if (nsl > 0) {
+        sell_width<<<ceil_div(nsl, 256), 256, 0, st>>>(A, nsl, w);
         DP_LAUNCH_CHECK();
-        exclusive_scan(st, w, S.nslices, tmp, &total);
+        std::vector<int64_t> hw(nsl);
+        DP_HIP(hipMemcpyAsync(hw.data(), w, sizeof(int64_t) * nsl, hipMemcpyDeviceToHost, st));
+        DP_HIP(hipStreamSynchronize(st));
+        for (int64_t x : hw) maxw = std::max(maxw, x / 64);
+        exclusive_scan(st, w, nsl, tmp, &total);
     }
-    S.nel = total;
-    sell_ptr<<<ceil_div(S.nslices + 1, 256), 256, 0, st>>>(w, S.nslices, total, S.sptr);
-    DP_LAUNCH_CHECK();
-    S.col = H.get<int>(total, what);
-    if (s->fp32) {
-        S.val = H.get<float>(total, what);
-        if (S.nslices)
-            sell_fill<float><<<S.nslices, 64, 0, st>>>(A, S.sptr, pad_self, S.col, (float*)S.val);
+    bool sell = total <= (int64_t)(1.3 * (double)A.nnz) + 64 && maxw <= 48;
+    size_t es = s->fp32 ? sizeof(float) : sizeof(double);
+    if (sell) {
+        op.kind = 0;
+        Sell& S = op.s;
+        S.n = A.n;
+        S.nslices = nsl;
+        S.nel = total;
+        S.sptr = H.get<int>(nsl + 1, what);
+        sell_ptr<<<ceil_div(nsl + 1, 256), 256, 0, st>>>(w, nsl, total, S.sptr);
+        DP_LAUNCH_CHECK();
+        S.col = H.get<int>(total, what);
+        S.val = H.take(es * (total > 0 ? total : 1), what);
+        if (nsl) {
+            if (s->fp32) sell_fill<float><<<nsl, 64, 0, st>>>(A, S.sptr, pad_self, S.col, (float*)S.val);
+            else sell_fill<double><<<nsl, 64, 0, st>>>(A, S.sptr, pad_self, S.col, (double*)S.val);
+            DP_LAUNCH_CHECK();
+        }
     } else {
-        S.val = H.get<double>(total, what);
-        if (S.nslices)
-            sell_fill<double><<<S.nslices, 64, 0, st>>>(A, S.sptr, pad_self, S.col, (double*)S.val);
+        op.kind = 1;
+        double mean = A.n > 0 ? (double)A.nnz / A.n : 1.0;
+        int G = 4;
+        while (G < 64 && G < mean) G <<= 1;
+        op.G = G;
+        op.rowptr = A.rowptr;
+        op.col = A.col;
+        if (s->fp32) {
+            op.val = H.get<float>(A.nnz, what);
+            if (A.nnz)
+                cast_vals<float><<<ceil_div(A.nnz, 256), 256, 0, st>>>(A.val, A.nnz, (float*)op.val);
+            DP_LAUNCH_CHECK();
+        } else {
+            op.val = A.val;
+        }
     }
-    DP_LAUNCH_CHECK();
     Sc.top = mark;
 }
 
@@ -815,8 +858,9 @@ void amg_setup(dp_sim* s) {
             int which = radix_sort(st, k0, v0, k1, v1, m, rbits + cbits, rtmp);
             uint64_t* ks = which ? k1 : k0;
             double* vs = which ? v1 : v0;
-            int64_t* flag = Sc.get<int64_t>(m, "rbk flag");
-            double* sums = Sc.get<double>(m, "rbk sums");
+            // the idle half of the sort's double buffer holds the run flags and sums
+            int64_t* flag = (int64_t*)(which ? k0 : k1);
+            double* sums = which ? v0 : v1;
             int* rowkey = Sc.get<int>(m, "rbk rows");
             Csr W;
             W.ncols = nc;
@@ -853,8 +897,8 @@ void amg_setup(dp_sim* s) {
             transpose_expand<<<ceil_div(n, 256), 256, 0, st>>>(L.P, rbits, k0, v0);
             DP_LAUNCH_CHECK();
             int which = radix_sort(st, k0, v0, k1, v1, m, rbits + cb, rtmp);
-            int64_t* flag = Sc.get<int64_t>(m, "rbk flag");
-            double* sums = Sc.get<double>(m, "rbk sums");
+            int64_t* flag = (int64_t*)(which ? k0 : k1);
+            double* sums = which ? v0 : v1;
             int* rowkey = Sc.get<int>(m, "rbk rows");
             R.ncols = n;
             reduce_to_csr(st, which ? k1 : k0, which ? v1 : v0, m, rbits, nc, flag, sums, rowkey, rtmp,
@@ -879,8 +923,8 @@ void amg_setup(dp_sim* s) {
             rap_expand<<<ceil_div(n, 256), 256, 0, st>>>(A, L.P, cnt, cb, k0, v0);
             DP_LAUNCH_CHECK();
             int which = radix_sort(st, k0, v0, k1, v1, m, 2 * cb, rtmp);
-            int64_t* flag = Sc.get<int64_t>(m, "rbk flag");
-            double* sums = Sc.get<double>(m, "rbk sums");
+            int64_t* flag = (int64_t*)(which ? k0 : k1);
+            double* sums = which ? v0 : v1;
             int* rowkey = Sc.get<int>(m, "rbk rows");
             Ac.ncols = nc;
             reduce_to_csr(st, which ? k1 : k0, which ? v1 : v0, m, cb, nc, flag, sums, rowkey, rtmp, H,
@@ -888,9 +932,10 @@ void amg_setup(dp_sim* s) {
         }
         Sc.top = smark;
         L.nc = nc;
-        build_sell(s, A, L.As, true, H, Sc, "A sell");
-        build_sell(s, L.P, L.Ps, false, H, Sc, "P sell");
-        build_sell(s, R, L.Rs, false, H, Sc, "R sell");
+        L.R = R;
+        build_op(s, A, L.Aop, true, H, Sc, "A apply");
+        build_op(s, L.P, L.Pop, false, H, Sc, "P apply");
+        build_op(s, R, L.Rop, false, H, Sc, "R apply");
         s->levels.push_back(L);
         A = Ac;
     }
@@ -944,11 +989,56 @@ __global__ void __launch_bounds__(256) dense_gemv(const T* __restrict__ M, int n
     if (lane == 0) y[row] = acc;
 }
 
+// CSR operator with G lanes per row; the G partial sums are combined by a
+// fixed butterfly inside the group.
+template <class T, int MODE, int G>
+__global__ void __launch_bounds__(256) csrv_kernel(const int* __restrict__ rowptr, const int* __restrict__ col,
+                                                   const T* __restrict__ val, int n,
+                                                   const T* __restrict__ dinv, const T* __restrict__ b,
+                                                   const T* __restrict__ x, T* y, T* y2) {
+    int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    int r = gid / G, l = gid % G;
+    if (r >= n) return;
+    T acc = 0;
+    for (int e = rowptr[r] + l; e < rowptr[r + 1]; e += G) {
+        int c = col[e];
+        T v = val[e];
+        if (MODE == SV_PRE) acc += v * (dinv[c] * b[c]);
+        else acc += v * x[c];
+    }
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
+    if (l != 0) return;
+    if (MODE == SV_Y) {
+        y[r] = acc;
+    } else if (MODE == SV_PRE) {
+        y[r] = dinv[r] * b[r];
+        y2[r] = b[r] - acc;
+    } else if (MODE == SV_PROL) {
+        y[r] += acc;
+    } else {
+        y[r] = x[r] + dinv[r] * (b[r] - acc);
+    }
+}
+
 template <class T, int MODE>
-static void sell_launch(dp_sim* s, const Sell& S, const T* dinv, const T* b, const T* x, T* y, T* y2) {
-    if (S.n == 0) return;
-    sell_kernel<T, MODE><<<ceil_div(S.n, 256), 256, 0, s->stream>>>(S.sptr, S.col, (const T*)S.val, S.n,
-                                                                    dinv, b, x, y, y2);
+static void op_launch(dp_sim* s, const Op& op, const T* dinv, const T* b, const T* x, T* y, T* y2) {
+    if (op.n == 0) return;
+    if (op.kind == 0) {
+        const Sell& S = op.s;
+        sell_kernel<T, MODE><<<ceil_div(S.n, 256), 256, 0, s->stream>>>(S.sptr, S.col, (const T*)S.val, S.n,
+                                                                        dinv, b, x, y, y2);
+    } else {
+        int grid = ceil_div((int64_t)op.n * op.G, 256);
+        const T* v = (const T*)op.val;
+        switch (op.G) {
+            case 4: csrv_kernel<T, MODE, 4><<<grid, 256, 0, s->stream>>>(op.rowptr, op.col, v, op.n, dinv, b, x, y, y2); break;
+            case 8: csrv_kernel<T, MODE, 8><<<grid, 256, 0, s->stream>>>(op.rowptr, op.col, v, op.n, dinv, b, x, y, y2); break;
+            case 16: csrv_kernel<T, MODE, 16><<<grid, 256, 0, s->stream>>>(op.rowptr, op.col, v, op.n, dinv, b, x, y, y2); break;
+            case 32: csrv_kernel<T, MODE, 32><<<grid, 256, 0, s->stream>>>(op.rowptr, op.col, v, op.n, dinv, b, x, y, y2); break;
+            default: csrv_kernel<T, MODE, 64><<<grid, 256, 0, s->stream>>>(op.rowptr, op.col, v, op.n, dinv, b, x, y, y2); break;
+        }
+    }
     DP_LAUNCH_CHECK();
 }
 
@@ -957,8 +1047,8 @@ T* amg_vcycle(dp_sim* s) {
     int L = (int)s->levels.size();
     for (int l = 0; l < L - 1; ++l) {
         AmgLevel& lv = s->levels[l];
-        sell_launch<T, SV_PRE>(s, lv.As, (T*)lv.dinv, (T*)lv.b, nullptr, (T*)lv.x, (T*)lv.r);
-        sell_launch<T, SV_Y>(s, lv.Rs, nullptr, nullptr, (T*)lv.r, (T*)s->levels[l + 1].b, nullptr);
+        op_launch<T, SV_PRE>(s, lv.Aop, (T*)lv.dinv, (T*)lv.b, nullptr, (T*)lv.x, (T*)lv.r);
+        op_launch<T, SV_Y>(s, lv.Rop, nullptr, nullptr, (T*)lv.r, (T*)s->levels[l + 1].b, nullptr);
     }
     AmgLevel& co = s->levels[L - 1];
     if (co.n > 0) {
@@ -969,8 +1059,8 @@ T* amg_vcycle(dp_sim* s) {
     T* xs = (T*)co.x;
     for (int l = L - 2; l >= 0; --l) {
         AmgLevel& lv = s->levels[l];
-        sell_launch<T, SV_PROL>(s, lv.Ps, nullptr, nullptr, xs, (T*)lv.x, nullptr);
-        sell_launch<T, SV_POST>(s, lv.As, (T*)lv.dinv, (T*)lv.b, (T*)lv.x, (T*)lv.t, nullptr);
+        op_launch<T, SV_PROL>(s, lv.Pop, nullptr, nullptr, xs, (T*)lv.x, nullptr);
+        op_launch<T, SV_POST>(s, lv.Aop, (T*)lv.dinv, (T*)lv.b, (T*)lv.x, (T*)lv.t, nullptr);
         xs = (T*)lv.t;
     }
     return xs;

@@ -97,10 +97,12 @@ void launch_decouple(dp_sim* s) {
 }
 
 // ---------------------------------------------------------------------------
-// Block SpMV.  MODE_Y: y = A x.  MODE_RES: y = b - A x.  MODE_RESP: yp = first
-// component of b - A x (reads only the pressure-row planes).  MODE_PROL:
-// x2 = x + (e, 0) (pressure correction prolonged from the AMG), y = b - A x2,
-// x2 written out.
+// Block SpMV.  MODE_Y: y = A x.  MODE_RES: y = b - A x.  MODE_PROL:
+// x2 = x + (e, 0), y = b - A x2, x2 written out, where e is the pressure
+// correction: e is given on the reduced pressure system (fracture rows, then
+// wells) and the matrix-node part is recovered as e_m = (r_m - a_mf e_f)/a_mm.
+// MODE_RESP (separate kernel below): the pressure residual restricted to the
+// reduced system.
 // ---------------------------------------------------------------------------
 enum { MODE_Y = 0, MODE_RES = 1, MODE_RESP = 2, MODE_PROL = 3 };
 
@@ -109,7 +111,8 @@ struct SpArgs {
     BMat<T> A;
     const V2<T>* x;
     const V2<T>* b;
-    const T* e;     // MODE_PROL: [nb] pressure correction
+    const T* e;     // MODE_PROL: [n + nw] pressure correction on the reduced system
+    const T* rpm;   // MODE_PROL: [n] matrix-node pressure residuals
     V2<T>* y;       // MODE_Y/RES/PROL
     T* yp;          // MODE_RESP
     V2<T>* x2;      // MODE_PROL
@@ -126,7 +129,14 @@ struct SpArgs {
 template <class T, int MODE>
 __device__ inline V2<T> xval(const SpArgs<T>& a, int pos) {
     V2<T> v = a.x[pos];
-    if (MODE == MODE_PROL) v.x += a.e[pos];
+    if (MODE == MODE_PROL) {
+        if (pos < a.n) {
+            T ef = a.e[a.frow[pos]];
+            v.x += (a.rpm[pos] - a.A.m0[pos].x * ef) / a.A.d0[pos].x;
+        } else {
+            v.x += a.e[pos - a.n];
+        }
+    }
     return v;
 }
 
@@ -209,6 +219,55 @@ __global__ void __launch_bounds__(256) spmv_kernel(SpArgs<T> a, int bm, int bf) 
     }
 }
 
+// Pressure residual of the reduced system: for fracture row q of cell c,
+// r_f = (b - A x)_f,0 and r_m = (b - A x)_m,0 (the two blocks of the matrix
+// row recomputed here), rr_q = r_f - a_fm (r_m / a_mm), r_m kept for the
+// back-substitution; for well w, rr_{n+w} = (b - A x)_w,0.  Only the pressure
+// rows of the blocks are read.
+template <class T>
+__global__ void __launch_bounds__(256) presid_red_kernel(SpArgs<T> a, int bf, T* rr, T* rpm) {
+    __shared__ T sh0[256 / WAVE];
+    int b = blockIdx.x;
+    int n = a.n;
+    if (b < bf) {
+        int q = b * blockDim.x + threadIdx.x;
+        if (q >= n) return;
+        int row = n + q;
+        int c = a.fcell[q];
+        T y0 = 0, dummy = 0;
+        acc_blk<T, MODE_RESP>(a.A.d0, a.A.d1, row, a.x[row], y0, dummy);
+#pragma unroll
+        for (int s = 0; s < 6; ++s)
+            acc_blk<T, MODE_RESP>(a.A.f0, a.A.f1, (int64_t)s * n + q, a.x[a.fcol[s * n + q]], y0, dummy);
+        V2<T> xm = a.x[c];
+        acc_blk<T, MODE_RESP>(a.A.f0, a.A.f1, (int64_t)6 * n + q, xm, y0, dummy);
+        int p = a.fperf[q];
+        if (p >= 0) acc_blk<T, MODE_RESP>(a.A.fw0, a.A.fw1, p, a.x[2 * n + a.perf_well[p]], y0, dummy);
+        T rf = a.b[row].x - y0;
+        T ym = 0;
+        acc_blk<T, MODE_RESP>(a.A.d0, a.A.d1, c, xm, ym, dummy);
+        acc_blk<T, MODE_RESP>(a.A.m0, a.A.m1, c, a.x[row], ym, dummy);
+        T rm = a.b[c].x - ym;
+        rpm[c] = rm;
+        rr[q] = rf - a.A.f0[(int64_t)6 * n + q].x * (rm / a.A.d0[c].x);
+    } else {
+        int w = b - bf;
+        int row = 2 * n + w;
+        T y0 = 0, dummy = 0;
+        for (int p = a.well_ptr[w] + threadIdx.x; p < a.well_ptr[w + 1]; p += blockDim.x)
+            acc_blk<T, MODE_RESP>(a.A.wf0, a.A.wf1, p, a.x[n + a.perf_q[p]], y0, dummy);
+        y0 = wave_sum(y0);
+        if (threadIdx.x % WAVE == 0) sh0[threadIdx.x / WAVE] = y0;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            T s0 = 0;
+            for (int i = 0; i < (int)(blockDim.x / WAVE); ++i) s0 += sh0[i];
+            acc_blk<T, MODE_RESP>(a.A.d0, a.A.d1, row, a.x[row], s0, dummy);
+            rr[n + w] = a.b[row].x - s0;
+        }
+    }
+}
+
 template <class T>
 static SpArgs<T> sp_args(dp_sim* s, const BMat<T>& A) {
     Topo& t = s->topo;
@@ -223,6 +282,7 @@ static SpArgs<T> sp_args(dp_sim* s, const BMat<T>& A) {
     a.well_ptr = t.well_ptr;
     a.n = t.n;
     a.nw = t.nw;
+    a.rpm = (const T*)s->rpm;
     return a;
 }
 
@@ -256,12 +316,13 @@ void bresidual(dp_sim* s, const V2<T>* b, const V2<T>* x, V2<T>* y) {
     sp_launch<T, MODE_RES>(s, a);
 }
 template <class T>
-void bresidual_p(dp_sim* s, const V2<T>* b, const V2<T>* x, T* yp) {
+void bresidual_p(dp_sim* s, const V2<T>* b, const V2<T>* x, T* rr) {
     SpArgs<T> a = sp_args<T>(s, amat<T>(s));
     a.x = x;
     a.b = b;
-    a.yp = yp;
-    sp_launch<T, MODE_RESP>(s, a);
+    int bf = ceil_div(s->topo.n, 256);
+    presid_red_kernel<T><<<bf + s->topo.nw, 256, 0, s->stream>>>(a, bf, rr, (T*)s->rpm);
+    DP_LAUNCH_CHECK();
 }
 template <class T>
 void bresidual_prol(dp_sim* s, const V2<T>* b, const V2<T>* x, const T* e, V2<T>* x2, V2<T>* y) {

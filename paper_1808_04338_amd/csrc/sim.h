@@ -81,12 +81,25 @@ struct Sell {
     void* val = nullptr;  // [nel] of the apply precision
 };
 
+// An operator of the V-cycle in the apply precision: SELL-64 when its rows are
+// short and even, else CSR processed by G lanes per row.
+struct Op {
+    int kind = 0;  // 0 SELL-64, 1 CSR with G lanes per row
+    int n = 0, G = 4;
+    int64_t nnz = 0;
+    Sell s;
+    int* rowptr = nullptr;
+    int* col = nullptr;
+    void* val = nullptr;
+};
+
 struct AmgLevel {
     int n = 0, nc = 0;
     Csr A;             // FP64 operator (setup)
     Csr P;             // FP64 interpolation n x nc (not on the coarsest level)
+    Csr R;             // FP64 restriction P^T
     int* cf = nullptr;  // [n] 1 = C, -1 = F
-    Sell As, Ps, Rs;    // apply copies
+    Op Aop, Pop, Rop;   // apply copies
     void* dinv = nullptr;  // [n] 1 / l1 diagonal
     void *x = nullptr, *b = nullptr, *r = nullptr, *t = nullptr;  // [n] work vectors
 };
@@ -129,7 +142,8 @@ struct dp_sim {
     dp::ILUF<double> ilu64;
     dp::ILUF<float> ilu32;
 
-    // level-0 pressure matrix structure (fixed) and its source map
+    // level-0 pressure matrix (fracture and well pressures after the exact
+    // elimination of the matrix-node pressures): fixed structure, source map
     dp::Csr Ap0;
     int* ap_src = nullptr;  // [nnz] source code of each entry
 
@@ -140,6 +154,7 @@ struct dp_sim {
 
     // preconditioner work vectors (apply precision), [nb] 2-vectors
     void *pr = nullptr, *pz = nullptr, *pt = nullptr, *pz2 = nullptr;
+    void* rpm = nullptr;  // [n] matrix-node pressure residuals of the current apply
     // GMRES (FP64)
     double* V = nullptr;   // [(restart+1) * 2nb]
     double* Z = nullptr;   // [restart * 2nb]

@@ -13,9 +13,9 @@ using namespace dp;
 
 namespace dp {
 
-// Average number of Galerkin products per level-0 pressure nonzero that the
-// setup scratch is sized for (the worst case is trunc^2 = 16).
-constexpr double RAP_EXPANSION = 10.0;
+// Galerkin products per level-0 pressure nonzero that the setup scratch is
+// sized for: the worst case trunc^2 with at most four interpolation entries.
+constexpr double RAP_EXPANSION = 16.0;
 constexpr int MAX_RED_BLOCKS_ALL = 1024;
 
 static void fill_defaults(dp_sim_desc& d) {
@@ -25,7 +25,7 @@ static void fill_defaults(dp_sim_desc& d) {
     if (d.amg_coarse_max <= 0) d.amg_coarse_max = 2000;
     if (d.amg_max_levels <= 0) d.amg_max_levels = 25;
     if (d.amg_theta <= 0) d.amg_theta = 0.25;
-    if (d.amg_trunc <= 0) d.amg_trunc = 4;
+    if (d.amg_trunc <= 0) d.amg_trunc = 3;
     if (d.newton_tol <= 0) d.newton_tol = 1e-8;
     if (d.max_newton <= 0) d.max_newton = 20;
     if (d.max_cuts <= 0) d.max_cuts = 8;
@@ -126,24 +126,21 @@ static void build_topology(const dp_sim_desc& d, HostTopo& h) {
         h.well_ptr[w + 1] = (int)h.perf_q.size();
     }
     h.nperf = (int)h.perf_q.size();
-    // level-0 pressure pattern (rows in elimination order, sorted columns)
-    h.ap_rowptr.assign(h.nb + 1, 0);
+    // level-0 pressure pattern of the reduced system (matrix-node pressures
+    // eliminated): rows = fracture rows q, then wells n + w; sorted columns
+    h.ap_rowptr.assign(n + h.nw + 1, 0);
     std::vector<std::pair<int, int>> row;
-    for (int r = 0; r < h.nb; ++r) {
+    for (int r = 0; r < n + h.nw; ++r) {
         row.clear();
         if (r < n) {
-            row.push_back({r, 0});
-            row.push_back({n + h.frow[r], 1});
-        } else if (r < 2 * n) {
-            int qq = r - n;
-            row.push_back({h.fcell[qq], 6});
+            int qq = r;
             for (int s = 0; s < 6; ++s)
-                if (h.fmask[qq] & (1u << s)) row.push_back({h.fcol[(size_t)s * n + qq], s});
-            row.push_back({r, 7});
-            if (h.fperf[qq] >= 0) row.push_back({2 * n + h.perf_well[h.fperf[qq]], 8});
+                if (h.fmask[qq] & (1u << s)) row.push_back({h.fcol[(size_t)s * n + qq] - n, s});
+            row.push_back({qq, 7});
+            if (h.fperf[qq] >= 0) row.push_back({n + h.perf_well[h.fperf[qq]], 8});
         } else {
-            int w = r - 2 * n;
-            for (int p = h.well_ptr[w]; p < h.well_ptr[w + 1]; ++p) row.push_back({n + h.perf_q[p], p});
+            int w = r - n;
+            for (int p = h.well_ptr[w]; p < h.well_ptr[w + 1]; ++p) row.push_back({h.perf_q[p], p});
             row.push_back({r, -1});
         }
         std::sort(row.begin(), row.end());
@@ -224,10 +221,10 @@ static Layout layout(dp_sim* s, Arena& a, const HostTopo& h) {
         alloc_ilu(a, s->ilu64, n, nb, nperf);
     }
     int64_t nnz0 = (int64_t)h.ap_col.size();
-    s->Ap0.n = nb;
-    s->Ap0.ncols = nb;
+    s->Ap0.n = n + nw;
+    s->Ap0.ncols = n + nw;
     s->Ap0.nnz = nnz0;
-    s->Ap0.rowptr = a.get<int>(nb + 1, "pressure pattern");
+    s->Ap0.rowptr = a.get<int>(n + nw + 1, "pressure pattern");
     s->Ap0.col = a.get<int>(nnz0, "pressure pattern");
     s->Ap0.val = a.get<double>(nnz0, "pressure pattern");
     s->ap_src = a.get<int>(nnz0, "pressure pattern");
@@ -235,6 +232,7 @@ static Layout layout(dp_sim* s, Arena& a, const HostTopo& h) {
     s->pz = a.take(es * 2 * nb, "precond vectors");
     s->pt = a.take(es * 2 * nb, "precond vectors");
     s->pz2 = a.take(es * 2 * nb, "precond vectors");
+    s->rpm = a.take(es * (n > 0 ? n : 1), "precond vectors");
     int m = s->restart;
     s->V = a.get<double>((int64_t)(m + 1) * 2 * nb, "krylov basis");
     s->Z = a.get<double>((int64_t)m * 2 * nb, "krylov basis");
@@ -249,8 +247,9 @@ static Layout layout(dp_sim* s, Arena& a, const HostTopo& h) {
     L.hier = (size_t)(4.0 * nnz0 * (12 + 1.5 * (4 + es)) + 2.0 * nb * (4 + 9 * es + 12 * 8) +
                       (double)cm * cm * es + (1 << 20));
     double expn = RAP_EXPANSION * nnz0;
-    L.scratch = (size_t)(expn * 52.0 + nnz0 * 24.0 + 8.0 * ((double)cm + 32) * ((double)cm + 32) +
-                         64.0 * nb + (4 << 20));
+    // per expanded product: keys and values twice (sort double buffer) + row key
+    L.scratch = (size_t)(expn * 36.0 + expn / 8.0 + nnz0 * 24.0 +
+                         8.0 * ((double)cm + 32) * ((double)cm + 32) + 64.0 * nb + (4 << 20));
     return L;
 }
 
@@ -1216,6 +1215,86 @@ dp_status sim_apply_stage(dp_sim* sim, int32_t stage, const double* r, double* z
         std::vector<double> zv = dl(sim, sim->V, n0);
         std::copy(zv.begin(), zv.end(), z);
     }
+    return DP_OK;
+    ABI_END(sim)
+}
+
+static double bench_bytes(dp_sim* s, int kernel) {
+    const Topo& t = s->topo;
+    double n = t.n, nb = t.nb, np = t.nperf;
+    double es = s->fp32 ? 4.0 : 8.0;
+    double blocks = nb + 7 * n + n + 2 * np;     // stored blocks of the matrix
+    double idx = 4.0 * (6 * n + 3 * n + 3 * np) + n;  // fcol, fcell, frow, fperf, perforations, fmask
+    double vec = 16.0 * nb;
+    if (kernel == 0) return blocks * 32.0 + idx + 2 * vec;
+    if (kernel == 1) {
+        // factors: U^-1 diagonals, L blocks (odd rows 7, even rows 1), U blocks taken
+        // from the matrix (even rows 6, matrix rows 1), perforation blocks
+        double fblocks = nb + 4 * n + 3 * n + n + 2 * np;
+        return fblocks * 4 * es + idx + 2 * nb * 2 * es;
+    }
+    if (kernel == 2) {
+        double b = 0;
+        for (size_t l = 0; l < s->levels.size(); ++l) {
+            const AmgLevel& L = s->levels[l];
+            if (l + 1 == s->levels.size()) {
+                b += (double)L.n * L.n * es + 2.0 * L.n * es;
+                break;
+            }
+            // two sweeps over A (pre: b, dinv gathered; post: x), P and R once,
+            // vectors: b, x, r, t, dinv
+            auto opb = [&](const Op& o) {
+                return o.kind == 0 ? o.s.nel * (4 + es) + 4.0 * (o.s.nslices + 1)
+                                   : o.nnz * (4 + es) + 4.0 * (o.n + 1);
+            };
+            b += 2.0 * opb(L.Aop) + opb(L.Pop) + opb(L.Rop);
+            b += 8.0 * L.n * es;
+        }
+        return b;
+    }
+    if (kernel == 3) {
+        // state, old accumulation, geometry read; residual and J written
+        return 16.0 * nb + 16.0 * 2 * n + 8.0 * (6 * n + 4 * n + np) + idx + 16.0 * nb +
+               blocks * 32.0;
+    }
+    return 0.0;
+}
+
+dp_status sim_bench_kernel(dp_sim* sim, int32_t kernel, int32_t reps, double* avg_ms, double* bytes) {
+    if (!sim || kernel < 0 || kernel > 4 || reps <= 0) return DP_E_INVALID;
+    ABI_BEGIN
+    if (sim->stage < 2) fail(DP_E_STATE, "kernel timing needs cpr_fpf_setup first");
+    int64_t len = 2 * (int64_t)sim->topo.nb;
+    auto launch = [&]() {
+        switch (kernel) {
+            case 0:
+                bspmv<double>(sim, (const d2*)sim->rhs, (d2*)sim->w);
+                break;
+            case 1:
+                if (sim->fp32) ilu_solve<float>(sim, (const f2*)sim->pr, (f2*)sim->pz);
+                else ilu_solve<double>(sim, (const d2*)sim->rhs, (d2*)sim->pz);
+                break;
+            case 2:
+                if (sim->fp32) amg_vcycle<float>(sim);
+                else amg_vcycle<double>(sim);
+                break;
+            case 3:
+                launch_assemble(sim, sim->dt_assembled);
+                break;
+            default:
+                cpr_apply(sim, (const double*)sim->rhs, sim->w);
+        }
+    };
+    if (sim->fp32) to_f32(sim, (const double*)sim->rhs, (float*)sim->pr, len);
+    launch();
+    DP_HIP(hipEventRecord(sim->ev0, sim->stream));
+    for (int r = 0; r < reps; ++r) launch();
+    DP_HIP(hipEventRecord(sim->ev1, sim->stream));
+    DP_HIP(hipEventSynchronize(sim->ev1));
+    float ms = 0.f;
+    DP_HIP(hipEventElapsedTime(&ms, sim->ev0, sim->ev1));
+    if (avg_ms) *avg_ms = ms / reps;
+    if (bytes) *bytes = bench_bytes(sim, kernel);
     return DP_OK;
     ABI_END(sim)
 }

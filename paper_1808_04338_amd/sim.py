@@ -66,7 +66,7 @@ def make_desc(model, precision=None, **opts):
     d.amg_coarse_max = int(opts.get("amg_coarse_max", 2000))
     d.amg_max_levels = int(opts.get("amg_max_levels", 25))
     d.amg_theta = float(opts.get("amg_theta", 0.25))
-    d.amg_trunc = int(opts.get("amg_trunc", 4))
+    d.amg_trunc = int(opts.get("amg_trunc", 3))
     d.newton_tol = float(opts.get("newton_tol", 1e-8))
     d.max_newton = int(opts.get("max_newton", 20))
     d.max_cuts = int(opts.get("max_cuts", 8))
@@ -249,6 +249,23 @@ class Sim:
         y = np.empty_like(x)
         self._chk(self.lib.sim_apply_matrix(self.h, _dp(x), _dp(y)))
         return y
+
+    KERNELS = ["block_spmv_f64", "block_ilu0_solve", "amg_vcycle", "assemble", "cpr_fpf_apply"]
+
+    def bench_kernel(self, kernel, reps=20):
+        """(average ms per launch, algorithmic bytes per launch) of a kernel group."""
+        ms = C.c_double()
+        b = C.c_double()
+        self._chk(self.lib.sim_bench_kernel(self.h, kernel, reps, C.byref(ms), C.byref(b)))
+        return ms.value, b.value
+
+    def bench_kernels(self, reps=20):
+        """All kernel groups; the entry with the largest time per apply first."""
+        out = []
+        for k, name in enumerate(self.KERNELS):
+            ms, b = self.bench_kernel(k, reps)
+            out.append(dict(name=name, ms=ms, bytes=b, gbs=(b / (ms * 1e-3) / 1e9) if b else None))
+        return out
 
     def enable_timing(self, on=True):
         self._chk(self.lib.sim_enable_timing(self.h, 1 if on else 0))

@@ -256,3 +256,25 @@ def test_cpr_gmres_matches_direct_solve():
         a, r = y[comp:4 * geo.n:2], yref[comp:4 * geo.n:2]
         assert np.abs(a - r).max() <= 1e-8 * np.abs(r).max()
     assert 1 <= its <= 30
+
+
+def test_reduced_pressure_solve_is_exact_with_one_level():
+    """Eliminating the matrix-node pressures is exact: with a one-level
+    hierarchy the pressure stage returns A_p^-1 r."""
+    geo, J, b = _system(synth.config0(), seed=5)
+    indptr, indices, data = ph.to_bsr(geo, J)
+    dh, _ = cpr.decouple(2 * geo.n, indptr, indices, data, b)
+    pc = cpr.CPRFPF(geo, indptr, indices, dh, amg_opts=dict(max_coarse=10 ** 6))
+    assert len(pc.amg.levels) == 1
+    assert pc.S.shape[0] == geo.n + geo.nw
+    rp = np.random.default_rng(3).standard_normal(pc.Ap.shape[0])
+    e = pc.pressure_solve(rp)
+    ref = spla.spsolve(pc.Ap.tocsc(), rp)
+    assert np.allclose(e, ref, rtol=1e-9, atol=1e-9 * np.abs(ref).max())
+    # the reduced matrix keeps the fracture/well pattern; only its diagonal changed
+    n = geo.n
+    blk = pc.App[n:, n:].tocsr()
+    blk.sort_indices()
+    assert np.array_equal(blk.indptr, pc.S.indptr) and np.array_equal(blk.indices, pc.S.indices)
+    off = blk.indices != np.repeat(np.arange(blk.shape[0]), np.diff(blk.indptr))
+    assert np.array_equal(blk.data[off], pc.S.data[off])
