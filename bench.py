@@ -3,9 +3,9 @@
 One step = one linear solve of an inexact-Newton iteration on the 60x220x85
 channelised dual-porosity model: residual/Jacobian assembly, CPR-FPF setup
 (decoupling, block ILU(0), pressure AMG) and GMRES(30) to a relative residual
-of 1e-6.  The Jacobian is the first Newton iterate of the step after two
-10-day timesteps, and it is re-assembled and set up from scratch in every
-step.  The headline value uses the FP32 preconditioner under the FP64 Krylov
+of 1e-6.  The Jacobian is taken at the third Newton iterate of the first
+10-day timestep (pressure transient under way, water entering at the
+injector) and is re-assembled and set up from scratch in every step.  The headline value uses the FP32 preconditioner under the FP64 Krylov
 loop; the plain FP64 form is measured in the same run.
 
 Prints one JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
@@ -52,12 +52,12 @@ def slab(model, nz):
     return m
 
 
-def prepare(sim, model, warm_steps):
-    """Advance warm_steps timesteps, then start a step: returns dt."""
+def prepare(sim, model, newton_its):
+    """Start the first timestep and take newton_its Newton iterations: returns dt."""
     dt = model["schedule"][0]
-    for _ in range(warm_steps):
-        sim.timestep(dt)
     sim.mark_old()
+    for _ in range(newton_its):
+        sim.newton_step(dt, 1e-6)
     return dt
 
 
@@ -74,14 +74,13 @@ def timed_form(model, precision, steps, warmup, rtol, state=None):
     from paper_1808_04338_amd import Sim
 
     sim = Sim(model, precision=precision, lin_rtol=rtol)
+    dt = model["schedule"][0]
+    sim.mark_old()  # the start of the first timestep: initial state
     if state is None:
-        dt = prepare(sim, model, 2)
+        prepare(sim, model, 3)
         state = sim.get_state()
     else:
         sim.set_state(*state)
-        sim.mark_old()
-        dt = model["schedule"][0]
-    # the start-of-step accumulation of the warm state
     for _ in range(warmup):
         one_solve(sim, dt, rtol)
     torch.cuda.synchronize()

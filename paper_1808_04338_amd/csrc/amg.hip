@@ -171,62 +171,75 @@ __global__ void interp_beta(Csr A, const unsigned char* __restrict__ smask, cons
     g[k] = cnt;
 }
 
-__global__ void interp_count(Csr A, const unsigned char* __restrict__ smask, const int* __restrict__ cf,
-                             const double* __restrict__ diag, const double* __restrict__ beta,
-                             const int* __restrict__ g, double* dd, int64_t* cnt) {
+// Row of every stored entry (thread per row).
+__global__ void entry_rows(Csr A, int* erow) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= A.n) return;
-    int64_t c = 0;
+    for (int e = A.rowptr[i]; e < A.rowptr[i + 1]; ++e) erow[e] = i;
+}
+
+// d_i of every F row: diagonal + weak entries + strong F entries whose row
+// cannot distribute (beta_k = 0); weak entries first, then those, column order.
+__global__ void interp_d(Csr A, const unsigned char* __restrict__ smask, const int* __restrict__ cf,
+                         const double* __restrict__ diag, const double* __restrict__ beta, double* dd) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= A.n) return;
     double d = diag[i];
     if (cf[i] < 0) {
         int b = A.rowptr[i], e1 = A.rowptr[i + 1];
         for (int e = b; e < e1; ++e) {
             int j = A.col[e];
-            if (j == i) continue;
-            if (!smask[e]) d += A.val[e];
+            if (j != i && !smask[e]) d += A.val[e];
         }
         for (int e = b; e < e1; ++e) {
             int j = A.col[e];
-            if (j == i || !smask[e]) continue;
-            if (cf[j] > 0) {
-                ++c;
-            } else if (beta[j] != 0.0) {
-                c += g[j];
-            } else {
-                d += A.val[e];
-            }
+            if (j != i && smask[e] && cf[j] < 0 && beta[j] == 0.0) d += A.val[e];
         }
     }
     dd[i] = d;
-    cnt[i] = c;
 }
 
-__global__ void interp_expand(Csr A, const unsigned char* __restrict__ smask, const int* __restrict__ cf,
-                              const int64_t* __restrict__ cidx, const double* __restrict__ diag,
-                              const double* __restrict__ beta, const int64_t* __restrict__ off, int cbits,
-                              uint64_t* keys, double* vals) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= A.n || cf[i] > 0) return;
-    int64_t o = off[i];
+// Number of products each stored entry (i, k) of an F row contributes to row i
+// of W: 1 for a strong C neighbour, g_k for a strong F neighbour with beta_k != 0.
+__global__ void interp_count_e(Csr A, const int* __restrict__ erow, const unsigned char* __restrict__ smask,
+                               const int* __restrict__ cf, const double* __restrict__ beta,
+                               const int* __restrict__ g, int64_t* cnt) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= A.nnz) return;
+    int i = erow[e];
+    int j = A.col[e];
+    int64_t c = 0;
+    if (cf[i] < 0 && j != i && smask[e]) {
+        if (cf[j] > 0) c = 1;
+        else if (beta[j] != 0.0) c = g[j];
+    }
+    cnt[e] = c;
+}
+
+__global__ void interp_expand_e(Csr A, const int* __restrict__ erow, const unsigned char* __restrict__ smask,
+                                const int* __restrict__ cf, const int64_t* __restrict__ cidx,
+                                const double* __restrict__ diag, const double* __restrict__ beta,
+                                const int64_t* __restrict__ off, int cbits, uint64_t* keys, double* vals) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= A.nnz) return;
+    int i = erow[e];
+    int j = A.col[e];
+    if (cf[i] > 0 || j == i || !smask[e]) return;
+    int64_t o = off[e];
     uint64_t rk = (uint64_t)i << cbits;
-    for (int e = A.rowptr[i]; e < A.rowptr[i + 1]; ++e) {
-        int j = A.col[e];
-        if (j == i || !smask[e]) continue;
-        double a = A.val[e];
-        if (cf[j] > 0) {
-            keys[o] = rk | (uint64_t)cidx[j];
-            vals[o] = a;
-            ++o;
-        } else if (beta[j] != 0.0) {
-            double bk = beta[j], dk = diag[j];
-            for (int f = A.rowptr[j]; f < A.rowptr[j + 1]; ++f) {
-                int jj = A.col[f];
-                double v = A.val[f];
-                if (smask[f] && cf[jj] > 0 && v * dk < 0.0) {
-                    keys[o] = rk | (uint64_t)cidx[jj];
-                    vals[o] = a * (v / bk);
-                    ++o;
-                }
+    double a = A.val[e];
+    if (cf[j] > 0) {
+        keys[o] = rk | (uint64_t)cidx[j];
+        vals[o] = a;
+    } else if (beta[j] != 0.0) {
+        double bk = beta[j], dk = diag[j];
+        for (int f = A.rowptr[j]; f < A.rowptr[j + 1]; ++f) {
+            int jj = A.col[f];
+            double v = A.val[f];
+            if (smask[f] && cf[jj] > 0 && v * dk < 0.0) {
+                keys[o] = rk | (uint64_t)cidx[jj];
+                vals[o] = a * (v / bk);
+                ++o;
             }
         }
     }
@@ -344,38 +357,30 @@ __global__ void transpose_expand(Csr P, int rbits, uint64_t* keys, double* vals)
     }
 }
 
-__global__ void rap_count(Csr A, Csr P, int64_t* cnt) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= A.n) return;
-    int64_t pi = P.rowptr[i + 1] - P.rowptr[i];
-    int64_t s = 0;
-    for (int e = A.rowptr[i]; e < A.rowptr[i + 1]; ++e) {
-        int k = A.col[e];
-        s += P.rowptr[k + 1] - P.rowptr[k];
-    }
-    cnt[i] = pi * s;
+// Products of stored entry (i, k): |P_i| |P_k|.
+__global__ void rap_count_e(Csr A, const int* __restrict__ erow, Csr P, int64_t* cnt) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= A.nnz) return;
+    int i = erow[e], k = A.col[e];
+    cnt[e] = (int64_t)(P.rowptr[i + 1] - P.rowptr[i]) * (P.rowptr[k + 1] - P.rowptr[k]);
 }
 
-// A_c(I,J) = sum_{i,k} P_iI a_ik P_kJ
-__global__ void rap_expand(Csr A, Csr P, const int64_t* __restrict__ off, int cbits, uint64_t* keys,
-                           double* vals) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= A.n) return;
-    int64_t o = off[i];
-    int pb = P.rowptr[i], pe = P.rowptr[i + 1];
-    if (pb == pe) return;
-    for (int e = A.rowptr[i]; e < A.rowptr[i + 1]; ++e) {
-        int k = A.col[e];
-        double a = A.val[e];
-        int qb = P.rowptr[k], qe = P.rowptr[k + 1];
-        for (int u = pb; u < pe; ++u) {
-            uint64_t rk = (uint64_t)P.col[u] << cbits;
-            double pa = P.val[u] * a;
-            for (int v = qb; v < qe; ++v) {
-                keys[o] = rk | (uint64_t)P.col[v];
-                vals[o] = pa * P.val[v];
-                ++o;
-            }
+// A_c(I,J) = sum_{i,k} P_iI a_ik P_kJ: entry (i, k) emits P_iI a_ik P_kJ.
+__global__ void rap_expand_e(Csr A, const int* __restrict__ erow, Csr P, const int64_t* __restrict__ off,
+                             int cbits, uint64_t* keys, double* vals) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= A.nnz) return;
+    int i = erow[e], k = A.col[e];
+    double a = A.val[e];
+    int64_t o = off[e];
+    int qb = P.rowptr[k], qe = P.rowptr[k + 1];
+    for (int u = P.rowptr[i]; u < P.rowptr[i + 1]; ++u) {
+        uint64_t rk = (uint64_t)P.col[u] << cbits;
+        double pa = P.val[u] * a;
+        for (int v = qb; v < qe; ++v) {
+            keys[o] = rk | (uint64_t)P.col[v];
+            vals[o] = pa * P.val[v];
+            ++o;
         }
     }
 }
@@ -461,55 +466,65 @@ __global__ void dense_fill(Csr A, int np, double* M) {
     M[idx] = v;
 }
 
-// Invert the 32x32 block M_kk into P (row-major 32x32) with partial pivoting.
-__global__ void __launch_bounds__(256) gj_diag(const double* __restrict__ M, int np, int kb, double* P,
-                                               int* bad) {
-    __shared__ double a[GJ_B][2 * GJ_B + 1];
-    __shared__ double mult[GJ_B];
-    __shared__ int piv;
-    int t = threadIdx.x;
+// Invert the 32x32 block M_kk into P (row-major 32x32) by Gauss-Jordan with
+// partial pivoting, in one wavefront: lane r (< 32) holds row r of [M_kk | I] in
+// registers (lanes 32..63 mirror rows 0..31); pivot search, row swap and
+// elimination use shuffles only.  Each pivot step is a template instance so
+// every register index is a compile-time constant.
+template <int C>
+__device__ __forceinline__ void gj_step(double (&a)[2 * GJ_B], int r, int rr, int* bad) {
+    double best = (r < GJ_B && rr >= C) ? fabs(a[C]) : -1.0;
+    int p = rr;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        double ob = __shfl_xor(best, o, WAVE);
+        int op = __shfl_xor(p, o, WAVE);
+        if (ob > best || (ob == best && op < p)) {
+            best = ob;
+            p = op;
+        }
+    }
+    if (best == 0.0 && r == 0) *bad = 1;
+    if (p != C) {
+        int src = (rr == C) ? p : ((rr == p) ? C : rr);
+#pragma unroll
+        for (int j = 0; j < 2 * GJ_B; ++j) a[j] = __shfl(a[j], src, WAVE);
+    }
+    double inv = 1.0 / __shfl(a[C], C, WAVE);
+    if (rr == C) {
+#pragma unroll
+        for (int j = 0; j < 2 * GJ_B; ++j) a[j] *= inv;
+    }
+    double f = a[C];
+#pragma unroll
+    for (int j = 0; j < 2 * GJ_B; ++j) {
+        double rcj = __shfl(a[j], C, WAVE);
+        if (rr != C) a[j] -= f * rcj;
+    }
+}
+
+template <int C>
+__device__ __forceinline__ void gj_steps(double (&a)[2 * GJ_B], int r, int rr, int* bad) {
+    if constexpr (C < GJ_B) {
+        gj_step<C>(a, r, rr, bad);
+        gj_steps<C + 1>(a, r, rr, bad);
+    }
+}
+
+__global__ void __launch_bounds__(64) gj_diag(const double* __restrict__ M, int np, int kb, double* P,
+                                              int* bad) {
+    int r = threadIdx.x;
+    int rr = r & (GJ_B - 1);
     int k0 = kb * GJ_B;
-    for (int i = t; i < GJ_B * 2 * GJ_B; i += 256) {
-        int r = i / (2 * GJ_B), c = i % (2 * GJ_B);
-        a[r][c] = c < GJ_B ? M[(int64_t)(k0 + r) * np + k0 + c] : (c - GJ_B == r ? 1.0 : 0.0);
-    }
-    __syncthreads();
-    for (int c = 0; c < GJ_B; ++c) {
-        if (t == 0) {
-            int p = c;
-            double best = fabs(a[c][c]);
-            for (int r = c + 1; r < GJ_B; ++r)
-                if (fabs(a[r][c]) > best) {
-                    best = fabs(a[r][c]);
-                    p = r;
-                }
-            piv = p;
-            if (best == 0.0) *bad = 1;
-        }
-        __syncthreads();
-        int p = piv;
-        if (p != c && t < 2 * GJ_B) {
-            double tmp = a[c][t];
-            a[c][t] = a[p][t];
-            a[p][t] = tmp;
-        }
-        __syncthreads();
-        double inv = 1.0 / a[c][c];
-        __syncthreads();
-        if (t < 2 * GJ_B) a[c][t] *= inv;
-        __syncthreads();
-        // elimination needs the multipliers of column c before any update
-        if (t < GJ_B) mult[t] = a[t][c];
-        __syncthreads();
-        for (int i = t; i < GJ_B * 2 * GJ_B; i += 256) {
-            int r = i / (2 * GJ_B), cc = i % (2 * GJ_B);
-            if (r != c) a[r][cc] -= mult[r] * a[c][cc];
-        }
-        __syncthreads();
-    }
-    for (int i = t; i < GJ_B * GJ_B; i += 256) {
-        int r = i / GJ_B, c = i % GJ_B;
-        P[i] = a[r][GJ_B + c];
+    double a[2 * GJ_B];
+#pragma unroll
+    for (int j = 0; j < GJ_B; ++j) a[j] = M[(int64_t)(k0 + rr) * np + k0 + j];
+#pragma unroll
+    for (int j = 0; j < GJ_B; ++j) a[GJ_B + j] = (j == rr) ? 1.0 : 0.0;
+    gj_steps<0>(a, r, rr, bad);
+    if (r < GJ_B) {
+#pragma unroll
+        for (int j = 0; j < GJ_B; ++j) P[r * GJ_B + j] = a[GJ_B + j];
     }
 }
 
@@ -634,7 +649,7 @@ void gj_invert(hipStream_t st, double* M, int np, double* P, double* C, int* bad
     int nbk = np / GJ_B;
     static const bool plain = getenv("DPSIM_GJ_PLAIN") != nullptr;
     for (int kb = 0; kb < nbk; ++kb) {
-        gj_diag<<<1, 256, 0, st>>>(M, np, kb, P, bad);
+        gj_diag<<<1, 64, 0, st>>>(M, np, kb, P, bad);
         if (plain) {
             gj_row<false><<<2 * nbk, 256, 0, st>>>(M, np, kb, P, C);
             gj_update<false><<<nbk * nbk, 256, 0, st>>>(M, np, kb, P, C);
@@ -838,13 +853,17 @@ void amg_setup(dp_sim* s) {
             double* beta = Sc.get<double>(n, "beta");
             int* g = Sc.get<int>(n, "g");
             double* dd = Sc.get<double>(n, "d");
-            int64_t* cnt = Sc.get<int64_t>(n + 1, "interp count");
             int64_t* stmp = Sc.get<int64_t>(scan_tmp_size(n + 1), "scan tmp");
+            int* erow = Sc.get<int>(A.nnz, "entry rows");
+            int64_t* ecnt = Sc.get<int64_t>(A.nnz + 1, "interp entry count");
+            int64_t* etmp = Sc.get<int64_t>(scan_tmp_size(A.nnz + 1), "scan tmp");
+            entry_rows<<<ceil_div(n, 256), 256, 0, st>>>(A, erow);
             interp_beta<<<ceil_div(n, 256), 256, 0, st>>>(A, smask, L.cf, diag, beta, g);
-            interp_count<<<ceil_div(n, 256), 256, 0, st>>>(A, smask, L.cf, diag, beta, g, dd, cnt);
+            interp_d<<<ceil_div(n, 256), 256, 0, st>>>(A, smask, L.cf, diag, beta, dd);
+            interp_count_e<<<ceil_div(A.nnz, 256), 256, 0, st>>>(A, erow, smask, L.cf, beta, g, ecnt);
             DP_LAUNCH_CHECK();
             int64_t m = 0;
-            exclusive_scan(st, cnt, n, stmp, &m);
+            exclusive_scan(st, ecnt, A.nnz, etmp, &m);
             int cbits = bits_for(nc);
             int rbits = bits_for(n);
             uint64_t* k0 = Sc.get<uint64_t>(m, "interp keys");
@@ -852,8 +871,8 @@ void amg_setup(dp_sim* s) {
             uint64_t* k1 = Sc.get<uint64_t>(m, "interp keys");
             double* v1 = Sc.get<double>(m, "interp vals");
             int64_t* rtmp = Sc.get<int64_t>(sort_tmp_size(m), "sort tmp");
-            interp_expand<<<ceil_div(n, 256), 256, 0, st>>>(A, smask, L.cf, cidx, diag, beta, cnt, cbits,
-                                                            k0, v0);
+            interp_expand_e<<<ceil_div(A.nnz, 256), 256, 0, st>>>(A, erow, smask, L.cf, cidx, diag, beta,
+                                                                  ecnt, cbits, k0, v0);
             DP_LAUNCH_CHECK();
             int which = radix_sort(st, k0, v0, k1, v1, m, rbits + cbits, rtmp);
             uint64_t* ks = which ? k1 : k0;
@@ -908,19 +927,21 @@ void amg_setup(dp_sim* s) {
         // Galerkin A_c = R A P
         Csr Ac;
         {
-            int64_t* cnt = Sc.get<int64_t>(n + 1, "rap count");
-            int64_t* stmp = Sc.get<int64_t>(scan_tmp_size(n + 1), "scan tmp");
-            rap_count<<<ceil_div(n, 256), 256, 0, st>>>(A, L.P, cnt);
+            int* erow = Sc.get<int>(A.nnz, "entry rows");
+            int64_t* cnt = Sc.get<int64_t>(A.nnz + 1, "rap count");
+            int64_t* stmp = Sc.get<int64_t>(scan_tmp_size(A.nnz + 1), "scan tmp");
+            entry_rows<<<ceil_div(n, 256), 256, 0, st>>>(A, erow);
+            rap_count_e<<<ceil_div(A.nnz, 256), 256, 0, st>>>(A, erow, L.P, cnt);
             DP_LAUNCH_CHECK();
             int64_t m = 0;
-            exclusive_scan(st, cnt, n, stmp, &m);
+            exclusive_scan(st, cnt, A.nnz, stmp, &m);
             int cb = bits_for(nc);
             uint64_t* k0 = Sc.get<uint64_t>(m, "rap keys");
             double* v0 = Sc.get<double>(m, "rap vals");
             uint64_t* k1 = Sc.get<uint64_t>(m, "rap keys");
             double* v1 = Sc.get<double>(m, "rap vals");
             int64_t* rtmp = Sc.get<int64_t>(sort_tmp_size(m) + scan_tmp_size(m + 1), "sort tmp");
-            rap_expand<<<ceil_div(n, 256), 256, 0, st>>>(A, L.P, cnt, cb, k0, v0);
+            rap_expand_e<<<ceil_div(A.nnz, 256), 256, 0, st>>>(A, erow, L.P, cnt, cb, k0, v0);
             DP_LAUNCH_CHECK();
             int which = radix_sort(st, k0, v0, k1, v1, m, 2 * cb, rtmp);
             int64_t* flag = (int64_t*)(which ? k0 : k1);

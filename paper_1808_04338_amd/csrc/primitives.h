@@ -16,8 +16,9 @@ int radix_sort(hipStream_t st, uint64_t* k0, double* v0, uint64_t* k1, double* v
                int bits, int64_t* tmp);
 
 // Sorted keys (row << cbits | col) and values -> CSR with nrows rows; equal keys
-// summed in order, zero sums dropped.  flag/sums/rowkey: scratch of n entries;
-// tmp: scan scratch.  The CSR arrays come from 'out'.
+// summed (fixed tree order), zero sums dropped.  flag/sums/rowkey: scratch of n
+// entries; tmp: scan scratch of at least max(scan_tmp_size(n), 2 ceil(n/64))
+// entries.  The CSR arrays come from 'out'.
 int64_t reduce_to_csr(hipStream_t st, const uint64_t* k, const double* v, int64_t n, int cbits,
                       int nrows, int64_t* flag, double* sums, int* rowkey, int64_t* tmp, Arena& out,
                       Csr& csr, const char* what);

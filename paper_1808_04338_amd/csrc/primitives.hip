@@ -211,16 +211,64 @@ __global__ void rbk_heads(const uint64_t* __restrict__ k, int64_t n, int64_t* fl
     if (i < n) flag[i] = (i == 0 || k[i] != k[i - 1]) ? 1 : 0;
 }
 
-// For each run head: sum the run; flag[i] := 1 if head and sum != 0.
-__global__ void rbk_sum(const uint64_t* __restrict__ k, const double* __restrict__ v, int64_t n,
-                        int64_t* flag, double* sums) {
+// Segmented sums of the sorted runs, computed by every element in parallel.
+// Pass 1 (per wave of 64 consecutive elements): inclusive segmented scan with a
+// fixed shuffle tree; each wave records the partial sum running off its end
+// (carry) and whether it holds a run start.  Pass 2: the last element of each
+// run adds, for a run that began in an earlier wave, the carries of the waves
+// back to the one holding its start.  The representative of a run is its last
+// element: flag = 1 there if the sum is nonzero.  Deterministic.
+__global__ void rbk_scan1(const uint64_t* __restrict__ k, const double* __restrict__ v, int64_t n,
+                          double* part, double* carry, int* wave_head) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int lane = threadIdx.x % WAVE;
+    bool valid = i < n;
+    uint64_t key = valid ? k[i] : 0;
+    bool head = valid && (i == 0 || key != k[i - 1]);
+    double val = valid ? v[i] : 0.0;
+    int flag = head ? 1 : 0;
+#pragma unroll
+    for (int d = 1; d < WAVE; d <<= 1) {
+        double pv = __shfl_up(val, d, WAVE);
+        int pf = __shfl_up(flag, d, WAVE);
+        if (lane >= d && !flag) {
+            val = pv + val;
+            flag = pf;
+        }
+    }
+    if (valid) part[i] = val;
+    uint64_t anyhead = __ballot(head);
+    int64_t w = i / WAVE;
+    if (lane == WAVE - 1 && (w * WAVE < n)) {
+        carry[w] = val;
+        wave_head[w] = anyhead != 0ull;
+    }
+}
+
+__global__ void rbk_scan2(const uint64_t* __restrict__ k, const double* __restrict__ part,
+                          const double* __restrict__ carry, const int* __restrict__ wave_head, int64_t n,
+                          int64_t* flag, double* sums) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    bool head = (i == 0 || k[i] != k[i - 1]);
+    uint64_t key = k[i];
+    bool last = (i == n - 1) || k[i + 1] != key;
     int64_t keep = 0;
-    if (head) {
-        double s = v[i];
-        for (int64_t j = i + 1; j < n && k[j] == k[i]; ++j) s += v[j];
+    if (last) {
+        double s = part[i];
+        // start of this run inside the wave?  (some element of the wave at or
+        // before i is the start of this run)
+        int64_t w = i / WAVE;
+        int64_t wstart = w * WAVE;
+        bool started_here = false;
+        // the run started in this wave iff the wave's first element is not part
+        // of it or is its start
+        if (wstart == 0 || k[wstart] != key || k[wstart - 1] != key) started_here = true;
+        if (!started_here) {
+            for (int64_t ww = w - 1; ww >= 0; --ww) {
+                s += carry[ww];
+                if (wave_head[ww]) break;
+            }
+        }
         sums[i] = s;
         keep = (s != 0.0) ? 1 : 0;
     }
@@ -274,7 +322,14 @@ int64_t reduce_to_csr(hipStream_t st, const uint64_t* k, const double* v, int64_
                       Csr& csr, const char* what) {
     int64_t total = 0;
     if (n > 0) {
-        rbk_sum<<<ceil_div(n, 256), 256, 0, st>>>(k, v, n, flag, sums);
+        // per-wave carries and flags in the scan scratch (free until the scan)
+        int64_t nwv = (n + WAVE - 1) / WAVE;
+        double* carry = (double*)(tmp);
+        int* whead = (int*)(tmp + nwv);
+        rbk_scan1<<<ceil_div(n, 256), 256, 0, st>>>(k, v, n, sums, carry, whead);
+        DP_LAUNCH_CHECK();
+        // pass 2 writes sums only at run ends, reading part (= sums) at i: in place
+        rbk_scan2<<<ceil_div(n, 256), 256, 0, st>>>(k, sums, carry, whead, n, flag, sums);
         DP_LAUNCH_CHECK();
         exclusive_scan(st, flag, n, tmp, &total);
     }
