@@ -130,6 +130,20 @@ def cpu_baseline(model, rtol, nz_sample):
     return t, geo.N, its
 
 
+def served_leg(count):
+    """Poisson arrivals (4/s), sizes uniform over five classes, 10 five-day steps
+    each, FP32 preconditioner, admission against a 200 GB budget."""
+    import synth
+    from paper_1808_04338_amd import Request, serve
+
+    stream = synth.served_stream(count=count)
+    reqs = [Request(r, synth.served_realisation(r, size), t, tag="%dx%dx%d" % size)
+            for t, r, size in stream]
+    _, summ = serve(reqs, budget_bytes=200 << 30, precision="fp32")
+    summ["unit"] = "timesteps/s"
+    return summ
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -140,6 +154,8 @@ def main():
     ap.add_argument("--cpu-layers", type=int, default=6)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--served", type=int, default=16,
+                    help="requests of the served-ensemble leg (0 to skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -200,6 +216,9 @@ def main():
         "kernels": r32["kern"],
         "cpu_baseline": cpu,
     }
+    if args.served > 0:
+        log("served ensemble: %d requests" % args.served)
+        out["served"] = served_leg(args.served)
     if r64 is not None:
         lat64 = np.array(r64["lat"]) * 1000.0
         out["fp64"] = {"value": args.steps / r64["wall"], "unit": "solves/s",

@@ -96,16 +96,20 @@ typedef struct {
     int32_t amg_max_levels;   /* [25] */
     double amg_theta;         /* [0.25] */
     int32_t amg_trunc;        /* interpolation entries kept per row [3], at most 8 */
-    double newton_tol;        /* scaled max-norm of the residual [1e-8] */
+    double newton_tol;        /* CNV: max over rows of |R| dt/(rho_ref phi V) (well rows scaled by
+                                 their target) [1e-3] */
     int32_t max_newton;       /* [20] */
     int32_t max_cuts;         /* [8] */
+    double mb_tol;            /* MB: per phase |sum_nodes R| dt / sum_nodes(rho_ref phi V) [1e-7];
+                                 Newton has converged when CNV <= newton_tol and MB <= mb_tol */
 } dp_sim_desc;
 
 typedef struct {
-    int32_t converged;   /* 1 if the residual met newton_tol before the update */
+    int32_t converged;   /* 1 if the residual met both tolerances before the update */
     int32_t lin_iters;   /* GMRES iterations of this step */
-    double res_scaled;   /* scaled max-norm of the residual at the start */
+    double res_scaled;   /* CNV of the residual at the start */
     double lin_rel_res;  /* final relative decoupled residual of GMRES */
+    double mb_scaled;    /* MB of the residual at the start (larger of the two phases) */
 } dp_newton_info;
 
 typedef struct {
@@ -138,8 +142,8 @@ const char *sim_last_error(const dp_sim *sim);
 dp_status sim_mark_old(dp_sim *sim);
 
 /* Residual R and Jacobian J at the current iterate for step length dt (Eq. (5)
- * discretised; Algorithm 1, "assemble b" and "compute A").  Writes the scaled
- * max-norm of R to *res_scaled if not NULL (synchronises). */
+ * discretised; Algorithm 1, "assemble b" and "compute A").  Writes the CNV of R
+ * to *res_scaled if not NULL (synchronises). */
 dp_status assemble_residual_jacobian(dp_sim *sim, double dt, double *res_scaled);
 
 /* Decouple (Eq. (14), Gauss-Jordan reading), factor block ILU(0), extract the

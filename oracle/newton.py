@@ -10,7 +10,8 @@ decoupled CPR-FPF GMRES (``linear='cpr'``, relative tolerance ``eta``).
 Readings (the paper does not state them): the update chops the saturation
 change of each node to at most 0.2 per iteration and then clamps S_w to [0, 1];
 BHP-controlled wells have p_b pinned to the target after every update;
-convergence is the scaled max-norm test below; at most ``max_newton``
+convergence is the scaled max-norm (CNV) together with the material-balance
+measure (MB) below; at most ``max_newton``
 iterations, then the step is cut in half (at most ``max_cuts`` times).  After a
 converged step a rate injector whose p_b exceeds its limit switches to BHP
 control at the limit and the step is repeated (at most once per step).
@@ -45,6 +46,16 @@ def scaled_residual_norm(geo, R, dt, control):
     return worst
 
 
+def material_balance_norm(geo, R, dt):
+    """max over phases of |sum over nodes of R_a| dt / sum over nodes (rho_a,ref phi V)."""
+    m = geo.m
+    n = geo.n
+    pv = np.sum(geo.vol * geo.phi)
+    mo = abs(np.sum(R[0:4 * n:2])) * dt / (m["rho_o_ref"] * pv)
+    mw = abs(np.sum(R[1:4 * n:2])) * dt / (m["rho_w_ref"] * pv)
+    return max(mo, mw)
+
+
 def apply_update(geo, x, dx, control):
     """x + dx with the saturation chop and clamp, and BHP pinning."""
     n = geo.n
@@ -60,8 +71,10 @@ def apply_update(geo, x, dx, control):
 
 
 def newton_solve(geo, x0, acc_old, dt, control, tol=1e-10, max_newton=20,
-                 linear="lu", eta=1e-10, cpr_opts=None):
-    """Newton iterations from x0.  Returns (x, converged, iterations, info)."""
+                 linear="lu", eta=1e-10, cpr_opts=None, mb_tol=1e-7):
+    """Newton iterations from x0.  Converged when the scaled max-norm (CNV) is at
+    most tol and the material-balance measure at most mb_tol.  Returns
+    (x, converged, iterations, info)."""
     x = x0.copy()
     info = {"res": [], "lin_iters": []}
     for it in range(max_newton + 1):
@@ -70,7 +83,7 @@ def newton_solve(geo, x0, acc_old, dt, control, tol=1e-10, max_newton=20,
         info["res"].append(nrm)
         if not np.isfinite(nrm):
             return x, False, it, info
-        if nrm <= tol:
+        if nrm <= tol and material_balance_norm(geo, R, dt) <= mb_tol:
             return x, True, it, info
         if it == max_newton:
             break

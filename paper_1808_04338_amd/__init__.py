@@ -6,3 +6,4 @@ arguments.  PyTorch supplies device memory and streams.
 """
 from ._lib import DpError, load  # noqa: F401
 from .sim import Sim, batch_timestep, footprint, make_desc  # noqa: F401
+from .serve import Request, serve  # noqa: F401,E402

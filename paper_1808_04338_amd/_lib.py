@@ -52,12 +52,13 @@ class DpSimDesc(C.Structure):
                 ("lin_maxit", C.c_int32), ("lin_rtol", C.c_double),
                 ("amg_coarse_max", C.c_int32), ("amg_max_levels", C.c_int32),
                 ("amg_theta", C.c_double), ("amg_trunc", C.c_int32),
-                ("newton_tol", C.c_double), ("max_newton", C.c_int32), ("max_cuts", C.c_int32)]
+                ("newton_tol", C.c_double), ("max_newton", C.c_int32), ("max_cuts", C.c_int32),
+                ("mb_tol", C.c_double)]
 
 
 class DpNewtonInfo(C.Structure):
     _fields_ = [("converged", C.c_int32), ("lin_iters", C.c_int32),
-                ("res_scaled", C.c_double), ("lin_rel_res", C.c_double)]
+                ("res_scaled", C.c_double), ("lin_rel_res", C.c_double), ("mb_scaled", C.c_double)]
 
 
 class DpStepInfo(C.Structure):

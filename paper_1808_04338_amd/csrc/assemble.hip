@@ -369,19 +369,21 @@ void launch_assemble(dp_sim* s, double dt) {
 }
 
 // ---------------------------------------------------------------------------
-// Scaled max-norm of the residual (convergence test)
-//   node rows: |R_a| dt / (rho_a,ref V phi); control rows: |R| * well_scale
-// NaN is propagated as +inf.
+// Convergence measures of the residual:
+//   CNV = max over node rows of |R_a| dt / (rho_a,ref V phi), control rows |R| *
+//         well_scale (NaN counts as +inf)
+//   sums over node rows of R_o and R_w (for the material-balance measure)
+// Block partials, then the last block combines them in block order.
 // ---------------------------------------------------------------------------
 __global__ void resnorm_kernel(const d2* __restrict__ R, const double* __restrict__ pvf,
                                const double* __restrict__ pvm, const int* __restrict__ fcell,
                                const double* __restrict__ well_scale, int n, int nw, double dt,
                                double rho_o, double rho_w, double* part, unsigned int* count,
                                double* out) {
-    __shared__ double sh[256 / WAVE];
+    __shared__ double sh[3][256 / WAVE];
     __shared__ bool last;
     int r = blockIdx.x * blockDim.x + threadIdx.x;
-    double v = 0.0;
+    double v = 0.0, so = 0.0, sw = 0.0;
     if (r < 2 * n) {
         double pv = r < n ? pvm[r] : pvf[fcell[r - n]];
         d2 x = R[r];
@@ -389,48 +391,86 @@ __global__ void resnorm_kernel(const d2* __restrict__ R, const double* __restric
         double b = fabs(x.y) * dt / (rho_w * pv);
         v = fmax(a, b);
         if (!(a == a) || !(b == b)) v = INFINITY;
+        so = x.x;
+        sw = x.y;
     } else if (r < 2 * n + nw) {
         double a = fabs(R[r].x) * well_scale[r - 2 * n];
         v = (a == a) ? a : INFINITY;
     }
     v = wave_max(v);
-    if (threadIdx.x % WAVE == 0) sh[threadIdx.x / WAVE] = v;
+    so = wave_sum(so);
+    sw = wave_sum(sw);
+    if (threadIdx.x % WAVE == 0) {
+        sh[0][threadIdx.x / WAVE] = v;
+        sh[1][threadIdx.x / WAVE] = so;
+        sh[2][threadIdx.x / WAVE] = sw;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
-        double m = 0.0;
-        for (int i = 0; i < (int)(blockDim.x / WAVE); ++i) m = fmax(m, sh[i]);
-        part[blockIdx.x] = m;
+        double m = 0.0, a = 0.0, b = 0.0;
+        for (int i = 0; i < (int)(blockDim.x / WAVE); ++i) {
+            m = fmax(m, sh[0][i]);
+            a += sh[1][i];
+            b += sh[2][i];
+        }
+        part[3 * (int64_t)blockIdx.x] = m;
+        part[3 * (int64_t)blockIdx.x + 1] = a;
+        part[3 * (int64_t)blockIdx.x + 2] = b;
         __threadfence();
         unsigned int ticket = atomicAdd(count, 1u);
         last = (ticket == gridDim.x - 1);
     }
     __syncthreads();
-    if (last) {
-        double m = 0.0;
-        for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x) m = fmax(m, part[i]);
-        m = wave_max(m);
-        if (threadIdx.x % WAVE == 0) sh[threadIdx.x / WAVE] = m;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double mm = 0.0;
-            for (int i = 0; i < (int)(blockDim.x / WAVE); ++i) mm = fmax(mm, sh[i]);
-            out[0] = mm;
-            *count = 0u;
+    if (!last) return;
+    __threadfence();
+    double m = 0.0, a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x) {
+        m = fmax(m, part[3 * (int64_t)i]);
+        a += part[3 * (int64_t)i + 1];
+        b += part[3 * (int64_t)i + 2];
+    }
+    m = wave_max(m);
+    a = wave_sum(a);
+    b = wave_sum(b);
+    __syncthreads();
+    if (threadIdx.x % WAVE == 0) {
+        sh[0][threadIdx.x / WAVE] = m;
+        sh[1][threadIdx.x / WAVE] = a;
+        sh[2][threadIdx.x / WAVE] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double mm = 0.0, aa = 0.0, bb = 0.0;
+        for (int i = 0; i < (int)(blockDim.x / WAVE); ++i) {
+            mm = fmax(mm, sh[0][i]);
+            aa += sh[1][i];
+            bb += sh[2][i];
         }
+        out[0] = mm;
+        out[1] = aa;
+        out[2] = bb;
+        *count = 0u;
     }
 }
 
-double residual_norm(dp_sim* s, double dt) {
+ResNorm residual_norm(dp_sim* s, double dt) {
     Topo& t = s->topo;
     int nblk = ceil_div(2 * t.n + t.nw, 256);
-    if (nblk > s->red_blocks) fail(DP_E_INVALID, "reduction buffer too small");
+    if (3 * nblk > 32 * s->red_blocks) fail(DP_E_INVALID, "reduction buffer too small");
     resnorm_kernel<<<nblk, 256, 0, s->stream>>>(s->res, t.pvf, t.pvm, t.fcell, t.well_scale, t.n,
                                                 t.nw, dt, s->rho_o_ref, s->rho_w_ref, s->red_part,
                                                 s->red_count, s->red_out);
     DP_LAUNCH_CHECK();
-    DP_HIP(hipMemcpyAsync(s->red_host, s->red_out, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    DP_HIP(hipMemcpyAsync(s->red_host, s->red_out, 3 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
     DP_HIP(hipStreamSynchronize(s->stream));
-    return s->red_host[0];
+    ResNorm r;
+    r.cnv = s->red_host[0];
+    double pv = s->pore_volume > 0 ? s->pore_volume : 1.0;
+    double mo = fabs(s->red_host[1]) * dt / (s->rho_o_ref * pv);
+    double mw = fabs(s->red_host[2]) * dt / (s->rho_w_ref * pv);
+    r.mb = fmax(mo, mw);
+    if (!(mo == mo) || !(mw == mw)) r.mb = INFINITY;
+    return r;
 }
 
 // ---------------------------------------------------------------------------

@@ -14,7 +14,11 @@ void launch_geometry(dp_sim* s, const double* kx, const double* ky, const double
                      const int* perf_cell, const double* perf_rw, const double* perf_skin);
 void launch_accumulation(dp_sim* s, const d2* x, d2* acc);
 void launch_assemble(dp_sim* s, double dt);
-double residual_norm(dp_sim* s, double dt);
+struct ResNorm {
+    double cnv;  // scaled max-norm
+    double mb;   // scaled material balance (larger phase)
+};
+ResNorm residual_norm(dp_sim* s, double dt);
 void launch_newton_update(dp_sim* s);
 
 // linalg.hip

@@ -26,7 +26,8 @@ static void fill_defaults(dp_sim_desc& d) {
     if (d.amg_max_levels <= 0) d.amg_max_levels = 25;
     if (d.amg_theta <= 0) d.amg_theta = 0.25;
     if (d.amg_trunc <= 0) d.amg_trunc = 3;
-    if (d.newton_tol <= 0) d.newton_tol = 1e-8;
+    if (d.newton_tol <= 0) d.newton_tol = 1e-3;
+    if (d.mb_tol <= 0) d.mb_tol = 1e-7;
     if (d.max_newton <= 0) d.max_newton = 20;
     if (d.max_cuts <= 0) d.max_cuts = 8;
 }
@@ -522,13 +523,19 @@ static void copy_state(dp_sim* s, const d2* from, d2* to) {
 
 static void mark_old(dp_sim* s) { launch_accumulation(s, s->x, s->acc_old); }
 
-static double assemble(dp_sim* s, double dt) {
+static ResNorm assemble(dp_sim* s, double dt) {
     PhaseScope ps(s, 0);
     launch_assemble(s, dt);
     s->dt_assembled = dt;
     s->stage = 1;
     return residual_norm(s, dt);
 }
+
+static bool converged(const dp_sim* s, const ResNorm& r) {
+    return r.cnv <= s->desc.newton_tol && r.mb <= s->desc.mb_tol;
+}
+
+static bool finite(const ResNorm& r) { return std::isfinite(r.cnv) && std::isfinite(r.mb); }
 
 static void setup(dp_sim* s) {
     if (s->stage < 1) fail(DP_E_STATE, "cpr_fpf_setup before assemble_residual_jacobian");
@@ -548,10 +555,10 @@ static int solve(dp_sim* s, double rtol, int maxit, int* its, double* rel) {
 static bool newton_loop(dp_sim* s, double h, int* newton_its, int* lin_its, double* res_out) {
     const dp_sim_desc& d = s->desc;
     for (int it = 0; it <= d.max_newton; ++it) {
-        double nrm = assemble(s, h);
-        *res_out = nrm;
-        if (!std::isfinite(nrm)) return false;
-        if (nrm <= d.newton_tol) return true;
+        ResNorm nrm = assemble(s, h);
+        *res_out = nrm.cnv;
+        if (!finite(nrm)) return false;
+        if (converged(s, nrm)) return true;
         if (it == d.max_newton) break;
         setup(s);
         int li = 0;
@@ -761,6 +768,11 @@ dp_status sim_create(const dp_sim_desc* desc, const double* p0, const double* sw
         up(prw, h.perf_rw.data(), sizeof(double) * h.nperf);
         up(psk, h.perf_skin.data(), sizeof(double) * h.nperf);
         launch_geometry(s, dk[0], dk[1], dk[2], dk[3], dk[4], dk[5], pc, prw, psk);
+        {
+            double vol = desc->dx * desc->dy * desc->dz, pv = 0.0;
+            for (int c = 0; c < n; ++c) pv += vol * desc->phi_f[c] + vol * desc->phi_m[c];
+            s->pore_volume = pv;
+        }
         std::vector<int> ctrl(h.nw);
         for (int w = 0; w < h.nw; ++w) ctrl[w] = s->wells[w].control;
         set_controls(s, ctrl);
@@ -824,9 +836,9 @@ dp_status sim_mark_old(dp_sim* sim) {
 dp_status assemble_residual_jacobian(dp_sim* sim, double dt, double* res_scaled) {
     if (!sim || !(dt > 0)) return DP_E_INVALID;
     ABI_BEGIN
-    double r = assemble(sim, dt);
-    if (res_scaled) *res_scaled = r;
-    return std::isfinite(r) ? DP_OK : DP_E_NUMERIC;
+    ResNorm r = assemble(sim, dt);
+    if (res_scaled) *res_scaled = r.cnv;
+    return finite(r) ? DP_OK : DP_E_NUMERIC;
     ABI_END(sim)
 }
 
@@ -866,14 +878,15 @@ dp_status newton_step(dp_sim* sim, double dt, double eta, dp_newton_info* info) 
     if (!sim || !(dt > 0) || !(eta > 0)) return DP_E_INVALID;
     ABI_BEGIN
     dp_newton_info o{};
-    double nrm = assemble(sim, dt);
-    o.res_scaled = nrm;
-    if (!std::isfinite(nrm)) {
+    ResNorm nrm = assemble(sim, dt);
+    o.res_scaled = nrm.cnv;
+    o.mb_scaled = nrm.mb;
+    if (!finite(nrm)) {
         if (info) *info = o;
         sim->err = "non-finite residual";
         return DP_E_NUMERIC;
     }
-    if (nrm <= sim->desc.newton_tol) {
+    if (converged(sim, nrm)) {
         o.converged = 1;
         if (info) *info = o;
         return DP_OK;

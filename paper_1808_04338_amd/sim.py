@@ -67,9 +67,10 @@ def make_desc(model, precision=None, **opts):
     d.amg_max_levels = int(opts.get("amg_max_levels", 25))
     d.amg_theta = float(opts.get("amg_theta", 0.25))
     d.amg_trunc = int(opts.get("amg_trunc", 3))
-    d.newton_tol = float(opts.get("newton_tol", 1e-8))
+    d.newton_tol = float(opts.get("newton_tol", 1e-3))
     d.max_newton = int(opts.get("max_newton", 20))
     d.max_cuts = int(opts.get("max_cuts", 8))
+    d.mb_tol = float(opts.get("mb_tol", 1e-7))
     return d, keep
 
 

@@ -1,0 +1,62 @@
+"""The served-ensemble scheduler with stand-in handles (no GPU): admission in
+arrival order by footprint, the memory budget is never exceeded, oversized
+requests are rejected, every step is accounted."""
+import threading
+import time
+
+import pytest
+
+from paper_1808_04338_amd.serve import Request, serve
+
+
+class FakeSim:
+    live = 0
+    peak = 0
+    lock = threading.Lock()
+
+    def __init__(self, model):
+        self.model = model
+        with FakeSim.lock:
+            FakeSim.live += model["fp"]
+            FakeSim.peak = max(FakeSim.peak, FakeSim.live)
+
+    def timestep(self, dt):
+        time.sleep(0.002 * self.model["cost"])
+        return {"newton_iters": 1, "lin_iters": 2}
+
+    def get_state(self):
+        return (self.model["name"],)
+
+    def close(self):
+        with FakeSim.lock:
+            FakeSim.live -= self.model["fp"]
+
+
+def _model(name, fp, cost, steps=3):
+    return {"name": name, "fp": fp, "cost": cost, "schedule": [1.0] * steps}
+
+
+def test_admission_respects_budget_and_order():
+    FakeSim.live = FakeSim.peak = 0
+    reqs = [Request(i, _model("m%d" % i, fp, 1 + i % 3), arrival=0.001 * i, tag=fp)
+            for i, fp in enumerate([4, 3, 5, 2, 6, 1, 4, 4])]
+    res, summ = serve(reqs, budget_bytes=10, max_active=3, sim_factory=FakeSim,
+                      footprint_fn=lambda m: m["fp"], keep_state=True)
+    assert summ["completed"] == len(reqs)
+    assert summ["timesteps"] == 3 * len(reqs)
+    assert FakeSim.peak <= 10
+    assert summ["peak_bytes"] <= 10 and summ["peak_active"] <= 3
+    # first-in first-out: admission times never decrease with arrival order
+    adm = [res[i].admitted for i in range(len(reqs))]
+    assert adm == sorted(adm)
+    for i in range(len(reqs)):
+        assert res[i].state == ("m%d" % i,)
+        assert len(res[i].latencies) == 3 and all(x >= 0 for x in res[i].latencies)
+
+
+def test_oversized_request_rejected_others_served():
+    reqs = [Request(0, _model("big", 50, 1), 0.0), Request(1, _model("ok", 5, 1), 0.0)]
+    res, summ = serve(reqs, budget_bytes=10, sim_factory=FakeSim, footprint_fn=lambda m: m["fp"])
+    assert res[0].status == "rejected"
+    assert res[1].status == "ok"
+    assert summ["rejected"] == 1 and summ["completed"] == 1
