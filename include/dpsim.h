@@ -157,8 +157,9 @@ dp_status cpr_fpf_setup(dp_sim *sim);
 dp_status krylov_solve(dp_sim *sim, double rtol, int32_t maxit, int32_t *iters,
                        double *rel_res);
 
-/* x <- x + y with the saturation chop (|dS| <= 0.2) and clamp to [0,1]; BHP
- * wells keep p_b at their target. */
+/* x <- x + y with the saturation chop (|dS| <= 0.2), a stop at the
+ * relative-permeability end point the change would cross from inside the
+ * mobile range, and the clamp to [0,1]; BHP wells keep p_b at their target. */
 dp_status newton_update(dp_sim *sim);
 
 /* One inexact-Newton iteration of Algorithm 1 with forcing term eta: assemble,

@@ -8,7 +8,8 @@ J y = -R is solved by SuperLU (``linear='lu'``) or by the oracle's own
 decoupled CPR-FPF GMRES (``linear='cpr'``, relative tolerance ``eta``).
 
 Readings (the paper does not state them): the update chops the saturation
-change of each node to at most 0.2 per iteration and then clamps S_w to [0, 1];
+change of each node to at most 0.2 per iteration, stops it at the
+relative-permeability end points it would cross, and clamps S_w to [0, 1];
 BHP-controlled wells have p_b pinned to the target after every update;
 convergence is the scaled max-norm (CNV) together with the material-balance
 measure (MB) below; at most ``max_newton``
@@ -57,12 +58,20 @@ def material_balance_norm(geo, R, dt):
 
 
 def apply_update(geo, x, dx, control):
-    """x + dx with the saturation chop and clamp, and BHP pinning."""
+    """x + dx with the saturation chop, the end-point stops and the clamp, and
+    BHP pinning.  A saturation change is limited to +-0.2; an update that
+    crosses S_wc from above stops at S_wc and one that crosses 1 - S_or from
+    below stops at 1 - S_or (the kinks of the relative permeabilities); the
+    result is clamped to [0, 1]."""
     n = geo.n
     m = geo.m
     y = x + dx
-    ds = np.clip(dx[1:4 * n:2], -SAT_CHOP, SAT_CHOP)
-    y[1:4 * n:2] = np.clip(x[1:4 * n:2] + ds, 0.0, 1.0)
+    s0 = x[1:4 * n:2]
+    s1 = s0 + np.clip(dx[1:4 * n:2], -SAT_CHOP, SAT_CHOP)
+    lo, hi = m["swc"], 1.0 - m["sor"]
+    s1 = np.where((s0 > lo) & (s1 < lo), lo, s1)
+    s1 = np.where((s0 < hi) & (s1 > hi), hi, s1)
+    y[1:4 * n:2] = np.clip(s1, 0.0, 1.0)
     for w, wl in enumerate(m["wells"]):
         if control[w] != "rate":
             y[4 * n + 2 * w] = wl["target"] if wl["control"] == "bhp" else wl["bhp_limit"]

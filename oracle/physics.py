@@ -209,10 +209,12 @@ def _phase_props(m, p, sw):
 def well_rates(geo, x, control):
     """Perforation mass rates into the fracture node (positive = injection).
 
-    Water injector: q_w = rho_w(p) W lambda_t (p_b - p), q_o = 0 (reading:
-    water-only injection with the block's total mobility).  Producer:
-    q_a = rho_a(p) W lambda_a (p_b - p) (Eq. (6), permeability counted once, in W).
-    Returns a list per well of (cells, q_o, q_w)."""
+    Producer, and an injector's perforation in back-flow (p_b < p):
+    q_a = rho_a(p) W lambda_a (p_b - p) with the block's phase mobilities (Eq. (6),
+    permeability counted once, in W).  Injecting perforation of a water injector
+    (p_b >= p): q_w = rho_w(p) W lambda_t (p_b - p), q_o = 0 (reading: water-only
+    injection with the block's total mobility; the mobility is taken from the
+    upstream side).  Returns a list per well of (cells, q_o, q_w)."""
     m = geo.m
     p, sw, bhp = unpack_state(x, geo.n)
     out = []
@@ -223,13 +225,13 @@ def well_rates(geo, x, control):
         rho_o, _, kro, _, mu_o = pr["o"]
         rho_w, _, krw, _, mu_w = pr["w"]
         dp = bhp[w] - pf
+        qo = rho_o * wi * (kro / mu_o) * dp
+        qw = rho_w * wi * (krw / mu_w) * dp
         if m["wells"][w]["kind"] == "inj":
+            inj = np.real(dp) >= 0.0
             lt = krw / mu_w + kro / mu_o
-            qw = rho_w * wi * lt * dp
-            qo = 0.0 * qw
-        else:
-            qo = rho_o * wi * (kro / mu_o) * dp
-            qw = rho_w * wi * (krw / mu_w) * dp
+            qw = np.where(inj, rho_w * wi * lt * dp, qw)
+            qo = np.where(inj, 0.0 * qw, qo)
         out.append((cells, qo, qw))
     return out
 
@@ -358,24 +360,24 @@ def jacobian(geo, x, dt, control):
         prw = _phase_props(m, pf, s)
         dp = bhp[w] - pf
         rw_idx = 4 * n + 2 * w
+        comps = []
+        for eq, ph in ((0, "o"), (1, "w")):
+            rho, drho, kr, dkr, mu = prw[ph]
+            lam = kr / mu
+            comps.append([eq, rho * wi * lam * dp,
+                          wi * lam * (drho * dp - rho),
+                          rho * wi * (dkr / mu) * dp,
+                          rho * wi * lam])
         if wl["kind"] == "inj":
+            inj = dp >= 0.0
             rho, drho, krw, dkrw, mu_w = prw["w"]
             _, _, kro, dkro, mu_o = prw["o"]
             lt = krw / mu_w + kro / mu_o
             dlt = dkrw / mu_w + dkro / mu_o
-            comps = [(1, rho * wi * lt * dp,
-                      wi * lt * (drho * dp - rho),
-                      rho * wi * dlt * dp,
-                      rho * wi * lt)]
-        else:
-            comps = []
-            for eq, ph in ((0, "o"), (1, "w")):
-                rho, drho, kr, dkr, mu = prw[ph]
-                lam = kr / mu
-                comps.append((eq, rho * wi * lam * dp,
-                              wi * lam * (drho * dp - rho),
-                              rho * wi * (dkr / mu) * dp,
-                              rho * wi * lam))
+            inj_w = (rho * wi * lt * dp, wi * lt * (drho * dp - rho), rho * wi * dlt * dp, rho * wi * lt)
+            for t in range(4):
+                comps[1][1 + t] = np.where(inj, inj_w[t], comps[1][1 + t])
+                comps[0][1 + t] = np.where(inj, 0.0, comps[0][1 + t])
         for eq, q, dq_dp, dq_ds, dq_db in comps:
             add(2 * node + eq, 2 * node, -dq_dp)
             add(2 * node + eq, 2 * node + 1, -dq_ds)

@@ -474,18 +474,22 @@ ResNorm residual_norm(dp_sim* s, double dt) {
 }
 
 // ---------------------------------------------------------------------------
-// Newton update: x += dx, saturation change chopped to +-0.2 and S clamped to
-// [0,1]; BHP wells pinned to their target; dummy unknowns kept at 0.
+// Newton update: x += dx; the saturation change is chopped to +-0.2, stopped at
+// the relative-permeability end point it would cross from inside the mobile
+// range (S_wc from above, 1 - S_or from below), and S is clamped to [0,1]; BHP
+// wells pinned to their target; dummy unknowns kept at 0.
 // ---------------------------------------------------------------------------
 __global__ void newton_update_kernel(d2* x, const d2* __restrict__ dx, int n, int nw,
                                      const int* __restrict__ well_ctrl,
-                                     const double* __restrict__ well_target) {
+                                     const double* __restrict__ well_target, double lo, double hi) {
     int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r < 2 * n) {
         d2 v = x[r];
         d2 d = dx[r];
         double ds = fmin(fmax(d.y, -0.2), 0.2);
         double s = v.y + ds;
+        if (v.y > lo && s < lo) s = lo;
+        if (v.y < hi && s > hi) s = hi;
         s = fmin(fmax(s, 0.0), 1.0);
         x[r] = mk2(v.x + d.x, s);
     } else if (r < 2 * n + nw) {
@@ -497,8 +501,8 @@ __global__ void newton_update_kernel(d2* x, const d2* __restrict__ dx, int n, in
 
 void launch_newton_update(dp_sim* s) {
     Topo& t = s->topo;
-    newton_update_kernel<<<ceil_div(t.nb, 256), 256, 0, s->stream>>>(s->x, s->dx, t.n, t.nw,
-                                                                    t.well_ctrl, t.well_target);
+    newton_update_kernel<<<ceil_div(t.nb, 256), 256, 0, s->stream>>>(
+        s->x, s->dx, t.n, t.nw, t.well_ctrl, t.well_target, s->swc, 1.0 - s->sor);
     DP_LAUNCH_CHECK();
 }
 

@@ -111,8 +111,10 @@ __device__ inline Transfer transfer(double tmf, double pf, const Props& f, doubl
     return t;
 }
 
-// Perforation mass rate into the fracture node (Eq. (6)): injector q_w =
-// rho_w W lambda_t (p_b - p), q_o = 0; producer q_a = rho_a W lambda_a (p_b - p).
+// Perforation mass rate into the fracture node (Eq. (6)), mobility from the
+// upstream side: an injecting perforation of a water injector (p_b >= p) gives
+// q_w = rho_w W lambda_t (p_b - p), q_o = 0; a producer, or an injector's
+// perforation in back-flow, gives q_a = rho_a W lambda_a (p_b - p).
 struct Perf {
     double q[2];
     double dp[2], ds[2], db[2];
@@ -122,7 +124,7 @@ __device__ inline Perf perf_rate(const Phys& P, int kind, double wi, double pb, 
                                  const Props& pr) {
     Perf r;
     double dpb = pb - p;
-    if (kind == DP_WELL_INJ) {
+    if (kind == DP_WELL_INJ && dpb >= 0.0) {
         double lt = pr.kr[1] / P.mu[1] + pr.kr[0] / P.mu[0];
         double dlt = pr.dkr[1] / P.mu[1] + pr.dkr[0] / P.mu[0];
         double rho = pr.rho[1];
