@@ -139,8 +139,10 @@ def served_leg(count):
     stream = synth.served_stream(count=count)
     reqs = [Request(r, synth.served_realisation(r, size), t, tag="%dx%dx%d" % size)
             for t, r, size in stream]
-    _, summ = serve(reqs, budget_bytes=200 << 30, precision="fp32")
+    res, summ = serve(reqs, budget_bytes=200 << 30, precision="fp32")
     summ["unit"] = "timesteps/s"
+    summ["failures"] = [{"rid": r.rid, "class": r.tag, "steps_done": len(r.latencies),
+                         "error": r.error} for r in res.values() if r.status != "ok"]
     return summ
 
 

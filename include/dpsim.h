@@ -61,8 +61,11 @@ typedef struct dp_sim dp_sim;
 /* A vertical well perforating the fracture nodes of cells (i, j, k0..k1).
  * Eq. (6): perforation rate q = rho W lambda (p_b - p); Eq. (7): well rate is
  * the sum over perforations; Eq. (8) with Eq. (10): W = 2 pi sqrt(kx ky) dz /
- * (ln(r_e/r_w) + skin), r_e Peaceman's.  An injector injects water only, with
- * the block's total mobility.  A rate-controlled injector whose converged p_b
+ * (ln(r_e/r_w) + skin), r_e Peaceman's.  Mobility is taken upstream: an
+ * injector's perforation with p_b >= p injects water only, with the block's
+ * total mobility; a perforation in back-flow produces each phase with the
+ * block's phase mobility.  Rate control fixes the well's net mass rate (both
+ * phases) at rho_w_ref * target.  A rate-controlled injector whose converged p_b
  * exceeds bhp_limit switches to BHP control at bhp_limit (once per step). */
 typedef struct {
     int32_t i, j, k0, k1;

@@ -17,6 +17,8 @@ iterations, then the step is cut in half (at most ``max_cuts`` times).  After a
 converged step a rate injector whose p_b exceeds its limit switches to BHP
 control at the limit and the step is repeated (at most once per step).
 """
+import warnings
+
 import numpy as np
 import scipy.sparse.linalg as spla
 
@@ -97,13 +99,21 @@ def newton_solve(geo, x0, acc_old, dt, control, tol=1e-10, max_newton=20,
         if it == max_newton:
             break
         J = ph.jacobian(geo, x, dt, control)
-        if linear == "lu":
-            dx = spla.spsolve(J.tocsc(), -R)
-            info["lin_iters"].append(1)
-        else:
-            from . import cpr
-            dx, its, _ = cpr.solve(geo, J, -R, rtol=eta, **(cpr_opts or {}))
-            info["lin_iters"].append(its)
+        # a singular or numerically failed linear stage counts as a failed iteration
+        try:
+            if linear == "lu":
+                with np.errstate(all="ignore"), warnings.catch_warnings():
+                    warnings.simplefilter("ignore", spla.MatrixRankWarning)
+                    dx = spla.spsolve(J.tocsc(), -R)
+                info["lin_iters"].append(1)
+            else:
+                from . import cpr
+                dx, its, _ = cpr.solve(geo, J, -R, rtol=eta, **(cpr_opts or {}))
+                info["lin_iters"].append(its)
+        except np.linalg.LinAlgError:
+            return x, False, it, info
+        if not np.all(np.isfinite(dx)):
+            return x, False, it, info
         x = apply_update(geo, x, dx, control)
     return x, False, max_newton, info
 

@@ -7,9 +7,10 @@ in Eq. (11)): every cell c = i + nx*(j + ny*k) carries two nodes, the fracture
 node 2c and the matrix node 2c+1.  Each node carries (p_o [Pa], S_w); the two
 equations of a node are the oil and water mass balances [kg/s].  Every well w
 carries its bottom-hole pressure p_b and a dummy unknown (so that all blocks
-are 2x2); its first equation is the control equation (rate: sum of the water
-perforation rates minus the target mass rate, Eqs. (6)-(7); BHP: p_b minus the
-target) and its second is ``dummy = 0``.
+are 2x2); its first equation is the control equation (rate: the well's net
+mass rate, the sum of both phases' perforation rates, minus the target water
+mass rate, Eqs. (6)-(7) -- while every perforation injects, the water rate;
+BHP: p_b minus the target) and its second is ``dummy = 0``.
 
 Global unknown index: node q -> (2q, 2q+1) = (p, S_w); well w -> (4n+2w,
 4n+2w+1) = (p_b, dummy).  Equation index: node q -> (2q, 2q+1) = (oil, water).
@@ -282,7 +283,7 @@ def residual(geo, x, acc_old, dt, control):
         np.add.at(Rw, 2 * cells, -qw)
         wl = m["wells"][w]
         if control[w] == "rate":
-            R[4 * n + 2 * w] = np.sum(qw) - m["rho_w_ref"] * wl["target"]
+            R[4 * n + 2 * w] = np.sum(qo + qw) - m["rho_w_ref"] * wl["target"]
         else:
             target = wl["target"] if wl["control"] == "bhp" else wl["bhp_limit"]
             R[4 * n + 2 * w] = bhp[w] - target
@@ -382,7 +383,7 @@ def jacobian(geo, x, dt, control):
             add(2 * node + eq, 2 * node, -dq_dp)
             add(2 * node + eq, 2 * node + 1, -dq_ds)
             add(2 * node + eq, rw_idx, -dq_db)
-            if control[w] == "rate" and eq == 1:
+            if control[w] == "rate":
                 add(rw_idx, 2 * node, dq_dp)
                 add(rw_idx, 2 * node + 1, dq_ds)
                 add(rw_idx, rw_idx, np.sum(dq_db))

@@ -270,7 +270,8 @@ __device__ void assemble_fracture_row(const AsmArgs& a, int q) {
     a.J.d1[pos] = mk2(D[1][0], D[1][1]);
 }
 
-// Well row w (one block): rate control sum_p q_w,p - rho_w,ref Q = 0, or BHP
+// Well row w (one block): rate control sum_p (q_o,p + q_w,p) - rho_w,ref Q = 0
+// (the net mass rate; the water rate while every perforation injects), or BHP
 // control p_b - target = 0; second row: dummy = 0.  The perforation sum is
 // reduced in a fixed order.
 __device__ void assemble_well_row(const AsmArgs& a, int w) {
@@ -285,10 +286,10 @@ __device__ void assemble_well_row(const AsmArgs& a, int w) {
         d2 xf = a.x[pos];
         Props pf = props(P, xf.x, xf.y);
         Perf r = perf_rate(P, a.well_kind[w], a.wi[p], xw.x, xf.x, pf);
-        q += r.q[1];
-        db += r.db[1];
+        q += r.q[0] + r.q[1];
+        db += r.db[0] + r.db[1];
         if (rate) {
-            a.J.wf0[p] = mk2(r.dp[1], r.ds[1]);
+            a.J.wf0[p] = mk2(r.dp[0] + r.dp[1], r.ds[0] + r.ds[1]);
         } else {
             a.J.wf0[p] = mk2(0.0, 0.0);
         }

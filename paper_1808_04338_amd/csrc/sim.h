@@ -173,4 +173,5 @@ struct dp_sim {
     bool timing = false;
     dp::PhaseTimer phase[5];
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t pev[5][2] = {};  // per-phase start/stop (phases nest)
 };

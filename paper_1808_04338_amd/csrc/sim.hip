@@ -352,14 +352,14 @@ struct PhaseScope {
     dp_sim* s;
     int ph;
     PhaseScope(dp_sim* s_, int ph_) : s(s_), ph(ph_) {
-        if (s->timing) DP_HIP(hipEventRecord(s->ev0, s->stream));
+        if (s->timing) DP_HIP(hipEventRecord(s->pev[ph][0], s->stream));
     }
     ~PhaseScope() {
         if (!s->timing) return;
-        if (hipEventRecord(s->ev1, s->stream) != hipSuccess) return;
-        if (hipEventSynchronize(s->ev1) != hipSuccess) return;
+        if (hipEventRecord(s->pev[ph][1], s->stream) != hipSuccess) return;
+        if (hipEventSynchronize(s->pev[ph][1]) != hipSuccess) return;
         float ms = 0.f;
-        if (hipEventElapsedTime(&ms, s->ev0, s->ev1) == hipSuccess) {
+        if (hipEventElapsedTime(&ms, s->pev[ph][0], s->pev[ph][1]) == hipSuccess) {
             s->phase[ph].total_ms += ms;
             s->phase[ph].count += 1;
         }
@@ -560,7 +560,13 @@ static bool newton_loop(dp_sim* s, double h, int* newton_its, int* lin_its, doub
         if (!finite(nrm)) return false;
         if (converged(s, nrm)) return true;
         if (it == d.max_newton) break;
-        setup(s);
+        // a singular preconditioner (zero pivot) counts as a failed iteration
+        try {
+            setup(s);
+        } catch (const Error& e) {
+            if (e.code != DP_E_NUMERIC) throw;
+            return false;
+        }
         int li = 0;
         double rr = 0;
         int st = solve(s, d.lin_rtol, d.lin_maxit, &li, &rr);
@@ -794,6 +800,8 @@ dp_status sim_create(const dp_sim_desc* desc, const double* p0, const double* sw
         up(s->x, xs.data(), sizeof(d2) * xs.size());
         DP_HIP(hipEventCreate(&s->ev0));
         DP_HIP(hipEventCreate(&s->ev1));
+        for (auto& pe : s->pev)
+            for (auto& e : pe) DP_HIP(hipEventCreate(&e));
         mark_old(s);
         DP_HIP(hipStreamSynchronize(st));
         sc.top = 0;
@@ -815,6 +823,9 @@ dp_status sim_destroy(dp_sim* sim) {
     if (!sim) return DP_OK;
     if (sim->ev0) (void)hipEventDestroy(sim->ev0);
     if (sim->ev1) (void)hipEventDestroy(sim->ev1);
+    for (auto& pe : sim->pev)
+        for (auto& e : pe)
+            if (e) (void)hipEventDestroy(e);
     delete sim;
     return DP_OK;
 }
