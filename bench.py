@@ -33,7 +33,7 @@ def log(*a):
 def make_model(nz):
     import synth
 
-    return synth.config2(nz=nz, steps=20)
+    return synth.model_channelised(nz=nz, steps=20)
 
 
 def slab(model, nz):

@@ -169,8 +169,10 @@ dp_status newton_update(dp_sim *sim);
  * and if not yet converged, setup + solve + update. */
 dp_status newton_step(dp_sim *sim, double dt, double eta, dp_newton_info *info);
 
-/* Advance the state by dt: Newton to convergence, halving dt on failure (at
- * most max_cuts times), well-control switching, material balance.  On
+/* Advance the state by dt: Newton to convergence, halving the sub-step on
+ * failure (at most max_cuts times in all) and doubling it again after each
+ * accepted sub-step (never beyond what remains of dt), well-control switching,
+ * material balance.  On
  * DP_E_NOCONV the state is rolled back to the start of the step. */
 dp_status timestep(dp_sim *sim, double dt, dp_step_info *info);
 

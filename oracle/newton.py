@@ -132,7 +132,9 @@ def _rel(err, mass):
 
 
 def timestep(geo, x, dt, control, max_cuts=8, **newton_kw):
-    """Advance by dt (possibly in several cut sub-steps).
+    """Advance by dt (possibly in several cut sub-steps).  A failed sub-step is
+    retried at half length; after an accepted one the length doubles again
+    (never beyond what remains of dt).
 
     Returns (x_new, report) where report lists every accepted sub-step with its
     material balance |M^{n+1} - M^n - dt Q(x^{n+1})| / M^{n+1} per phase."""
@@ -178,6 +180,7 @@ def timestep(geo, x, dt, control, max_cuts=8, **newton_kw):
                            control=list(control)))
         x = xn
         remaining -= h
+        h *= 2.0  # after an accepted sub-step the next may be twice as long
     return x, report, control
 
 

@@ -638,6 +638,7 @@ static int do_timestep(dp_sim* s, double dt, dp_step_info* info) {
         out.substeps += 1;
         remaining -= h;
         out.dt += h;
+        h *= 2.0;  // after an accepted sub-step the next may be twice as long
         hsub = dl(s, s->x, s->topo.nb);
     }
     out.cuts = cuts;

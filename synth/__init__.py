@@ -11,10 +11,10 @@ from .models import (  # noqa: F401
     DAY,
     base_physics,
     make_model,
-    config0,
-    config1,
-    config2,
-    config3,
+    model_small,
+    model_layered,
+    model_channelised,
+    model_channelised_fp32,
     served_size_classes,
     served_stream,
     served_realisation,

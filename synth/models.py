@@ -54,7 +54,9 @@ def _well(i, j, k0, k1, kind, control, target, bhp_limit=60.0e6, rw=0.0762, skin
 
 def make_model(nx, ny, nz, dx, dy, dz, kx, ky, kz, km, phi_f, phi_m, wells,
                schedule, p_init=30.0e6, sw_init=None, **overrides):
-    """Assemble a model dict with uniform initial pressure and S_w = S_wc."""
+    """Assemble a model dict with S_w = S_wc and a hydrostatic initial pressure:
+    p_init in the top layer, rising by rho_o,ref * gravity * dz per layer (the
+    same value in the fracture and matrix node of a cell)."""
     m = base_physics()
     m.update(overrides)
     n = nx * ny * nz
@@ -65,7 +67,9 @@ def make_model(nx, ny, nz, dx, dy, dz, kx, ky, kz, km, phi_f, phi_m, wells,
         m[name] = a.copy()
     m["wells"] = list(wells)
     m["schedule"] = [float(t) for t in schedule]
-    m["p0"] = np.full(2 * n, float(p_init))
+    layer = np.arange(n) // (nx * ny)
+    p_cell = float(p_init) + m["rho_o_ref"] * m["gravity"] * float(dz) * layer
+    m["p0"] = np.repeat(p_cell, 2)
     m["sw0"] = np.full(2 * n, float(m["swc"] if sw_init is None else sw_init))
     return m
 
@@ -76,7 +80,7 @@ def _porosities(rng, n):
     return phi_f, phi_m
 
 
-def config0(seed=0):
+def model_small(seed=0):
     """10x10x3, 1200 DOF: i.i.d. lognormal fields, one injector, one BHP producer."""
     nx, ny, nz = 10, 10, 3
     n = nx * ny * nz
@@ -124,12 +128,12 @@ def layered_model(nx, ny, nz, seed, rate_each, schedule):
                       _five_spot(nx, ny, nz, rate_each), schedule)
 
 
-def config1(seed=1):
+def model_layered(seed=1):
     """60x60x10, 144k DOF: layered lognormal field, five-spot (4 injectors, 1 producer)."""
     return layered_model(60, 60, 10, seed, 1000.0 / DAY, [5.0 * DAY] * 30)
 
 
-def config2(seed=2, nx=60, ny=220, nz=85, steps=20):
+def model_channelised(seed=2, nx=60, ny=220, nz=85, steps=20):
     """60x220x85, 4.49M DOF: channelised fracture field (30% channels along y)."""
     rng = _rng(seed)
     n = nx * ny * nz
@@ -156,9 +160,9 @@ def config2(seed=2, nx=60, ny=220, nz=85, steps=20):
     return m
 
 
-def config3(seed=2, **kw):
-    """Same model as config2 (identical seed); the preconditioner runs in FP32."""
-    m = config2(seed, **kw)
+def model_channelised_fp32(seed=2, **kw):
+    """Same model as model_channelised (identical seed); the preconditioner runs in FP32."""
+    m = model_channelised(seed, **kw)
     m["precond_precision"] = "fp32"
     return m
 
@@ -168,10 +172,11 @@ def served_size_classes():
 
 
 def served_realisation(r, size):
-    """Realisation r of the served ensemble: configs-1 physics at the given size."""
+    """Realisation r of the served ensemble: the layered five-spot model of
+    model_layered at the given size, with the same injection rate per
+    perforated layer (100 m^3/day) and ten 5-day steps."""
     nx, ny, nz = size
-    n = nx * ny * nz
-    return layered_model(nx, ny, nz, 1000 + r, 1000.0 * (n / 36000.0) / DAY, [5.0 * DAY] * 10)
+    return layered_model(nx, ny, nz, 1000 + r, 100.0 * nz / DAY, [5.0 * DAY] * 10)
 
 
 def served_stream(count=256, rate=4.0, seed=4, classes=None):

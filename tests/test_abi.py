@@ -77,10 +77,10 @@ def test_footprint_is_host_only_and_grows_with_size():
     from paper_1808_04338_amd import footprint
 
     _lib()
-    f0 = footprint(synth.config0())
-    f1 = footprint(synth.config1())
+    f0 = footprint(synth.model_small())
+    f1 = footprint(synth.model_layered())
     assert 0 < f0 < f1
-    assert footprint(synth.config0(), "fp32") <= f0 + (1 << 20)
+    assert footprint(synth.model_small(), "fp32") <= f0 + (1 << 20)
 
 
 def test_invalid_descriptors_are_rejected():
@@ -88,7 +88,7 @@ def test_invalid_descriptors_are_rejected():
     from paper_1808_04338_amd._lib import DP_E_INVALID, DpError
 
     _lib()
-    m = synth.config0()
+    m = synth.model_small()
     bad = dict(m, nx=0)
     with pytest.raises(DpError) as e:
         footprint(bad)
@@ -108,7 +108,7 @@ def test_create_rejects_null_workspace_without_touching_a_gpu():
     L, lib = _lib()
     from paper_1808_04338_amd.sim import _dp, make_desc
 
-    m = synth.config0()
+    m = synth.model_small()
     d, keep = make_desc(m)
     h = C.c_void_p()
     p0 = np.ascontiguousarray(m["p0"])

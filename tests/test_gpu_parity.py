@@ -19,7 +19,7 @@ from oracle import physics as oph
 pytestmark = pytest.mark.gpu
 
 MODELS = {
-    "c0": lambda: synth.config0(),
+    "c0": lambda: synth.model_small(),
     "tiny_grav": lambda: synth.model_tiny(4, 3, 2, seed=3),
     "tiny_nowell": lambda: synth.model_tiny(3, 2, 2, seed=4, wells=False),
     "column": lambda: synth.model_tiny(2, 1, 6, seed=5),
@@ -47,7 +47,7 @@ def test_assembly_matches_oracle(name):
 
 
 def test_assembly_medium_model():
-    m = synth.config1()
+    m = synth.model_layered()
     x, x_old = random_state_pair(m, 7)
     dt = 5 * synth.DAY
     geo, R, J = oracle_system(m, x, x_old, dt)
@@ -91,7 +91,7 @@ def test_decoupling_and_ilu_match_oracle(name):
 def test_amg_hierarchy_matches_oracle():
     """Identical C/F splittings at every level (a deterministic rule), P and the
     Galerkin operators to 1e-10, on the 144k-DOF model."""
-    m = synth.config1()
+    m = synth.model_layered()
     x, x_old = random_state_pair(m, 5)
     dt = 5 * synth.DAY
     geo, R, J = oracle_system(m, x, x_old, dt)
@@ -119,7 +119,7 @@ def test_amg_hierarchy_matches_oracle():
 
 @pytest.mark.parametrize("name", ["c0", "tiny_grav", "medium"])
 def test_preconditioner_and_gmres_match_oracle(name):
-    m = synth.config1() if name == "medium" else MODELS[name]()
+    m = synth.model_layered() if name == "medium" else MODELS[name]()
     x, x_old = random_state_pair(m, 9)
     dt = synth.DAY
     geo, R, J = oracle_system(m, x, x_old, dt)
@@ -154,7 +154,7 @@ def test_dense_coarse_inverse_selftest():
 def test_one_level_hierarchy_is_exact():
     """With the coarse limit above the system size, the pressure stage is an
     exact solve (dense MFMA Gauss-Jordan inverse)."""
-    m = synth.config0()
+    m = synth.model_small()
     x, x_old = random_state_pair(m, 2)
     geo, R, J = oracle_system(m, x, x_old, synth.DAY)
     sim = sim_at(m, x, x_old, synth.DAY, amg_coarse_max=4000)
@@ -219,7 +219,7 @@ def test_deterministic_and_checkpoint_restore():
     """Two runs are bitwise equal; 2 steps = 1 step, checkpoint, restore, 1 step."""
     from paper_1808_04338_amd import Sim
 
-    m = synth.config0()
+    m = synth.model_small()
     dt = m["schedule"][0]
     a = Sim(m)
     a.timestep(dt)
@@ -247,7 +247,7 @@ def test_mixed_precision_bound():
     the bound set by the tolerances."""
     from paper_1808_04338_amd import Sim
 
-    m = synth.config0()
+    m = synth.model_small()
     dt = m["schedule"][0]
     s32 = Sim(m, precision="fp32", newton_tol=1e-10, lin_rtol=1e-10)
     geo = oph.Geometry(m)
@@ -273,7 +273,7 @@ def test_error_paths():
     from paper_1808_04338_amd import Sim
     from paper_1808_04338_amd._lib import DP_E_STATE, DpError
 
-    m = synth.config0()
+    m = synth.model_small()
     sim = Sim(m)
     with pytest.raises(DpError) as e:
         sim.solve(1e-6, 10)

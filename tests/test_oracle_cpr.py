@@ -21,7 +21,7 @@ def _system(m, seed=3, dt=synth.DAY):
 
 
 def test_decoupling_definition():
-    geo, J, b = _system(synth.config0())
+    geo, J, b = _system(synth.model_small())
     indptr, indices, data = ph.to_bsr(geo, J)
     dh, bh = cpr.decouple(2 * geo.n, indptr, indices, data, b)
     Ah = ph.bsr_to_csr(indptr, indices, dh)
@@ -88,7 +88,7 @@ def test_bilu0_exact_without_fill():
 def test_default_ordering_matrix_nodes_eliminated_exactly():
     """Matrix nodes first: each couples only to its own fracture node, so their
     elimination is exact and the fracture diagonal becomes the Schur complement."""
-    geo, J, b = _system(synth.config0())
+    geo, J, b = _system(synth.model_small())
     indptr, indices, data = ph.to_bsr(geo, J)
     perm = cpr.default_ordering(geo)
     ilu = cpr.BlockILU0(indptr, indices, data, perm)
@@ -180,7 +180,7 @@ def test_interpolation_reproduces_constants_on_zero_row_sums():
 
 
 def test_amg_galerkin_and_exact_coarse():
-    geo, J, b = _system(synth.config0())
+    geo, J, b = _system(synth.model_small())
     indptr, indices, data = ph.to_bsr(geo, J)
     dh, _ = cpr.decouple(2 * geo.n, indptr, indices, data, b)
     Ap = cpr.pressure_matrix(indptr, indices, dh)
@@ -241,13 +241,13 @@ def test_gmres_finite_termination_diagonal():
 
 
 def test_cpr_with_exact_full_stage_converges_in_one_iteration():
-    geo, J, b = _system(synth.config0())
+    geo, J, b = _system(synth.model_small())
     y, its, rel = cpr.solve(geo, J, b, rtol=1e-10, exact_f=True)
     assert its == 1
 
 
 def test_cpr_gmres_matches_direct_solve():
-    geo, J, b = _system(synth.config0(), seed=11)
+    geo, J, b = _system(synth.model_small(), seed=11)
     y, its, rel = cpr.solve(geo, J, b, rtol=1e-12)
     yref = spla.spsolve(J.tocsc(), b)
     assert rel <= 1e-12
@@ -261,7 +261,7 @@ def test_cpr_gmres_matches_direct_solve():
 def test_reduced_pressure_solve_is_exact_with_one_level():
     """Eliminating the matrix-node pressures is exact: with a one-level
     hierarchy the pressure stage returns A_p^-1 r."""
-    geo, J, b = _system(synth.config0(), seed=5)
+    geo, J, b = _system(synth.model_small(), seed=5)
     indptr, indices, data = ph.to_bsr(geo, J)
     dh, _ = cpr.decouple(2 * geo.n, indptr, indices, data, b)
     pc = cpr.CPRFPF(geo, indptr, indices, dh, amg_opts=dict(max_coarse=10 ** 6))

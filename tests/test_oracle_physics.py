@@ -22,7 +22,7 @@ def test_paper_constants_golden():
     conv = {"lbm/ft3": lbm_ft3, "ft": 0.3048}
     bp = synth.base_physics()
     used = {"water_density": bp["rho_w_ref"], "oil_density": bp["rho_o_ref"],
-            "well_radius": synth.config0()["wells"][0]["rw"], "top_depth": bp["top_depth"]}
+            "well_radius": synth.model_small()["wells"][0]["rw"], "top_depth": bp["top_depth"]}
     for line in open(os.path.join(GOLDEN, "paper_constants.txt")):
         if line.startswith("#") or not line.strip():
             continue
@@ -70,7 +70,7 @@ def test_transmissibility_closed_forms():
 
 
 def test_face_counts():
-    m = synth.config0()
+    m = synth.model_small()
     geo = ph.Geometry(m)
     nx, ny, nz = m["nx"], m["ny"], m["nz"]
     assert geo.fc.shape[0] == (nx - 1) * ny * nz + nx * (ny - 1) * nz + nx * ny * (nz - 1)
@@ -89,7 +89,7 @@ def test_peaceman_golden():
 def test_peaceman_symmetry_and_well_index():
     kx, ky = 300 * synth.MD, 30 * synth.MD
     assert ph.peaceman_re(20.0, 10.0, kx, ky) == pytest.approx(ph.peaceman_re(10.0, 20.0, ky, kx), rel=1e-15)
-    m = synth.config0()
+    m = synth.model_small()
     perfs = ph.well_perforations(m)
     cells, wi = perfs[0]
     c = cells[0]
@@ -167,7 +167,7 @@ def test_jacobian_central_differences():
 
 
 def test_jacobian_in_block_pattern():
-    m = synth.config0()
+    m = synth.model_small()
     geo = ph.Geometry(m)
     x = ph.pack_state(*synth.random_state(m, 3))
     J = ph.jacobian(geo, x, synth.DAY, _ctrl(m))
@@ -222,8 +222,8 @@ def test_single_cell_equilibrium():
     assert acc[1].sum() == pytest.approx(mtot, rel=1e-13)
 
 
-def test_material_balance_config0():
-    geo, states, reports = nt.run(synth.config0())
+def test_material_balance_small_model():
+    geo, states, reports = nt.run(synth.model_small())
     for rep in reports:
         for r in rep:
             assert r["mb_oil"] <= 1e-10 and r["mb_water"] <= 1e-10
