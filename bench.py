@@ -68,7 +68,7 @@ def one_solve(sim, dt, rtol):
     return its, rel
 
 
-def timed_form(model, precision, steps, warmup, rtol, state=None):
+def timed_form(model, precision, steps, warmup, rtol, state=None, kernels=True):
     import torch
 
     from paper_1808_04338_amd import Sim
@@ -101,7 +101,7 @@ def timed_form(model, precision, steps, warmup, rtol, state=None):
     phases = {name: sim.phase_time(i)[0] for i, name in enumerate(
         ["assembly_ms", "setup_ms", "solve_ms", "spmv_ms_total", "precond_ms_total"])}
     sim.enable_timing(False)
-    kern = sim.bench_kernels(20)
+    kern = sim.bench_kernels(20) if kernels else []
     levels = sim.amg_info()
     out = dict(wall=wall, lat=lat, iters=its_l, rel=rel, phases=phases, kern=kern,
                amg_rows=[int(r) for r in levels[1]], amg_nnz=[int(r) for r in levels[2]],
@@ -156,6 +156,8 @@ def main():
     ap.add_argument("--cpu-layers", type=int, default=6)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-kernels", action="store_true",
+                    help="skip the per-kernel timings (kernels list and roofline)")
     ap.add_argument("--served", type=int, default=16,
                     help="requests of the served-ensemble leg (0 to skip)")
     args = ap.parse_args()
@@ -169,7 +171,8 @@ def main():
     log("generating the 60x220x%d model" % args.nz)
     model = make_model(args.nz)
     log("FP32-preconditioner form")
-    r32, state = timed_form(model, "fp32", args.steps, args.warmup, args.rtol)
+    r32, state = timed_form(model, "fp32", args.steps, args.warmup, args.rtol,
+                            kernels=not args.no_kernels)
     r64 = None
     if not args.no_fp64:
         log("FP64 form")
@@ -178,11 +181,13 @@ def main():
     value = args.steps / r32["wall"]
     lat = np.array(r32["lat"]) * 1000.0
     kern = {k["name"]: k for k in r32["kern"]}
-    k = kern[ROOFLINE_KERNEL]
-    roof = dict(bound="hbm", kernel=k["name"], achieved=k["bytes"] / (k["ms"] * 1e-3) / 1e9,
-                peak=HBM_PEAK_GBS, unit="GB/s", traffic=None, bytes_per_launch=k["bytes"],
-                avg_ms=k["ms"])
-    roof["frac"] = roof["achieved"] / roof["peak"]
+    roof = None
+    if ROOFLINE_KERNEL in kern:
+        k = kern[ROOFLINE_KERNEL]
+        roof = dict(bound="hbm", kernel=k["name"], achieved=k["bytes"] / (k["ms"] * 1e-3) / 1e9,
+                    peak=HBM_PEAK_GBS, unit="GB/s", traffic=None, bytes_per_launch=k["bytes"],
+                    avg_ms=k["ms"])
+        roof["frac"] = roof["achieved"] / roof["peak"]
     cpu = None
     if not args.no_cpu:
         log("oracle CPU baseline on a %d-layer slab" % args.cpu_layers)
