@@ -68,12 +68,12 @@ def one_solve(sim, dt, rtol):
     return its, rel
 
 
-def timed_form(model, precision, steps, warmup, rtol, state=None, kernels=True):
+def timed_form(model, precision, steps, warmup, rtol, state=None, kernels=True, **opts):
     import torch
 
     from paper_1808_04338_amd import Sim
 
-    sim = Sim(model, precision=precision, lin_rtol=rtol)
+    sim = Sim(model, precision=precision, lin_rtol=rtol, **opts)
     dt = model["schedule"][0]
     sim.mark_old()  # the start of the first timestep: initial state
     if state is None:
@@ -156,6 +156,8 @@ def main():
     ap.add_argument("--cpu-layers", type=int, default=6)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--amg-coarse-max", type=int, default=0,
+                    help="largest coarsest AMG level (0: the library default)")
     ap.add_argument("--no-kernels", action="store_true",
                     help="skip the per-kernel timings (kernels list and roofline)")
     ap.add_argument("--served", type=int, default=16,
@@ -171,12 +173,16 @@ def main():
     log("generating the 60x220x%d model" % args.nz)
     model = make_model(args.nz)
     log("FP32-preconditioner form")
+    opts = {}
+    if args.amg_coarse_max:
+        opts["amg_coarse_max"] = args.amg_coarse_max
     r32, state = timed_form(model, "fp32", args.steps, args.warmup, args.rtol,
-                            kernels=not args.no_kernels)
+                            kernels=not args.no_kernels, **opts)
     r64 = None
     if not args.no_fp64:
         log("FP64 form")
-        r64, _ = timed_form(model, "fp64", args.steps, args.warmup, args.rtol, state=state)
+        r64, _ = timed_form(model, "fp64", args.steps, args.warmup, args.rtol, state=state,
+                            kernels=not args.no_kernels, **opts)
     ms = 1000.0 * r32["wall"] / args.steps
     value = args.steps / r32["wall"]
     lat = np.array(r32["lat"]) * 1000.0

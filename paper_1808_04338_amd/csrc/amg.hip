@@ -467,64 +467,72 @@ __global__ void dense_fill(Csr A, int np, double* M) {
 }
 
 // Invert the 32x32 block M_kk into P (row-major 32x32) by Gauss-Jordan with
-// partial pivoting, in one wavefront: lane r (< 32) holds row r of [M_kk | I] in
-// registers (lanes 32..63 mirror rows 0..31); pivot search, row swap and
-// elimination use shuffles only.  Each pivot step is a template instance so
-// every register index is a compile-time constant.
+// partial pivoting, in one wavefront: lane j holds column j of [M_kk | I] (64
+// columns, 64 lanes) in registers.  The pivot search runs in every lane on its
+// own column and lane C's answer is broadcast with readlane; the row swap, the
+// scaling and the elimination are register operations on every column, with
+// the factors a[r][C] broadcast from lane C.  Each pivot step is a template
+// instance so that every register index is a compile-time constant.
+__device__ __forceinline__ double lane_bcast(double v, int l) {
+    long long b = __builtin_bit_cast(long long, v);
+    int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), l);
+    int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (long long)(unsigned int)lo);
+}
+
 template <int C>
-__device__ __forceinline__ void gj_step(double (&a)[2 * GJ_B], int r, int rr, int* bad) {
-    double best = (r < GJ_B && rr >= C) ? fabs(a[C]) : -1.0;
-    int p = rr;
+__device__ __forceinline__ void gj_step(double (&a)[GJ_B], int* bad) {
+    double best = fabs(a[C]);
+    int p = C;
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        double ob = __shfl_xor(best, o, WAVE);
-        int op = __shfl_xor(p, o, WAVE);
-        if (ob > best || (ob == best && op < p)) {
-            best = ob;
-            p = op;
+    for (int r = C + 1; r < GJ_B; ++r) {
+        double v = fabs(a[r]);
+        if (v > best) {
+            best = v;
+            p = r;
         }
     }
-    if (best == 0.0 && r == 0) *bad = 1;
-    if (p != C) {
-        int src = (rr == C) ? p : ((rr == p) ? C : rr);
+    p = __builtin_amdgcn_readlane(p, C);
+    if (lane_bcast(best, C) == 0.0 && threadIdx.x == 0) *bad = 1;
 #pragma unroll
-        for (int j = 0; j < 2 * GJ_B; ++j) a[j] = __shfl(a[j], src, WAVE);
+    for (int r = C + 1; r < GJ_B; ++r) {
+        if (r == p) {
+            double t = a[C];
+            a[C] = a[r];
+            a[r] = t;
+        }
     }
-    double inv = 1.0 / __shfl(a[C], C, WAVE);
-    if (rr == C) {
+    double inv = 1.0 / lane_bcast(a[C], C);
+    a[C] *= inv;
 #pragma unroll
-        for (int j = 0; j < 2 * GJ_B; ++j) a[j] *= inv;
-    }
-    double f = a[C];
-#pragma unroll
-    for (int j = 0; j < 2 * GJ_B; ++j) {
-        double rcj = __shfl(a[j], C, WAVE);
-        if (rr != C) a[j] -= f * rcj;
+    for (int r = 0; r < GJ_B; ++r) {
+        if (r != C) {
+            double f = lane_bcast(a[r], C);
+            a[r] = fma(-f, a[C], a[r]);
+        }
     }
 }
 
 template <int C>
-__device__ __forceinline__ void gj_steps(double (&a)[2 * GJ_B], int r, int rr, int* bad) {
+__device__ __forceinline__ void gj_steps(double (&a)[GJ_B], int* bad) {
     if constexpr (C < GJ_B) {
-        gj_step<C>(a, r, rr, bad);
-        gj_steps<C + 1>(a, r, rr, bad);
+        gj_step<C>(a, bad);
+        gj_steps<C + 1>(a, bad);
     }
 }
 
 __global__ void __launch_bounds__(64) gj_diag(const double* __restrict__ M, int np, int kb, double* P,
                                               int* bad) {
-    int r = threadIdx.x;
-    int rr = r & (GJ_B - 1);
+    int j = threadIdx.x;
     int k0 = kb * GJ_B;
-    double a[2 * GJ_B];
+    double a[GJ_B];
 #pragma unroll
-    for (int j = 0; j < GJ_B; ++j) a[j] = M[(int64_t)(k0 + rr) * np + k0 + j];
+    for (int r = 0; r < GJ_B; ++r)
+        a[r] = j < GJ_B ? M[(int64_t)(k0 + r) * np + k0 + j] : (r == j - GJ_B ? 1.0 : 0.0);
+    gj_steps<0>(a, bad);
+    if (j >= GJ_B) {
 #pragma unroll
-    for (int j = 0; j < GJ_B; ++j) a[GJ_B + j] = (j == rr) ? 1.0 : 0.0;
-    gj_steps<0>(a, r, rr, bad);
-    if (r < GJ_B) {
-#pragma unroll
-        for (int j = 0; j < GJ_B; ++j) P[r * GJ_B + j] = a[GJ_B + j];
+        for (int r = 0; r < GJ_B; ++r) P[r * GJ_B + (j - GJ_B)] = a[r];
     }
 }
 

@@ -112,6 +112,11 @@ __host__ __device__ inline Blk<T> bsub(const Blk<T>& a, const Blk<T>& b) {
     return Blk<T>{a.a00 - b.a00, a.a01 - b.a01, a.a10 - b.a10, a.a11 - b.a11};
 }
 
+template <class T>
+__host__ __device__ inline Blk<T> badd(const Blk<T>& a, const Blk<T>& b) {
+    return Blk<T>{a.a00 + b.a00, a.a01 + b.a01, a.a10 + b.a10, a.a11 + b.a11};
+}
+
 // Inverse of a 2x2 block by the adjugate formula.
 template <class T>
 __host__ __device__ inline Blk<T> binv(const Blk<T>& a) {

@@ -9,7 +9,7 @@ namespace dp {
 
 constexpr int KMAX = 32;  // restart <= 30: at most 31 basis vectors
 constexpr int RBLK = 256;
-constexpr int MAX_RED_BLOCKS = 1024;
+constexpr int MAX_RED_BLOCKS = 2048;
 
 struct Coef {
     double c[KMAX];
@@ -29,85 +29,132 @@ __device__ inline double block_sum(double v, double* sh) {
 // OP 1: w -= sum_k h_k V_k; out_k = V_k . w        (one read of every V_k)
 // OP 2: w -= sum_k h_k V_k; out_0 = w . w
 // OP 3: out_0 = w . w
-template <int OP>
+// NV bounds nv at compile time so that the per-thread accumulators of a short
+// basis stay few (occupancy); every thread handles (x, y) pairs (16-byte loads).
+// len is even and V, w are 16-byte aligned with an even leading dimension.
+template <int OP, int NV>
 __global__ void __launch_bounds__(RBLK) red_kernel(const double* __restrict__ V, int64_t ld, int nv,
                                                    const double* __restrict__ h, double* w, int64_t len,
                                                    double* part, unsigned int* count, double* out) {
-    __shared__ double sh[RBLK / WAVE];
+    __shared__ double sh[NV][RBLK / WAVE];
     __shared__ bool last;
-    double acc[KMAX];
-    double hh[KMAX];
+    double acc[NV];
+    double hh[NV];
 #pragma unroll
-    for (int k = 0; k < KMAX; ++k) {
+    for (int k = 0; k < NV; ++k) {
         acc[k] = 0.0;
         hh[k] = (OP == 1 || OP == 2) && k < nv ? h[k] : 0.0;
     }
+    const int64_t half = len >> 1;
+    const int64_t ld2 = ld >> 1;
+    const double2* V2 = reinterpret_cast<const double2*>(V);
+    double2* w2 = reinterpret_cast<double2*>(w);
     const int64_t stride = (int64_t)gridDim.x * RBLK;
-    for (int64_t i = (int64_t)blockIdx.x * RBLK + threadIdx.x; i < len; i += stride) {
-        double wi = w[i];
+    for (int64_t i = (int64_t)blockIdx.x * RBLK + threadIdx.x; i < half; i += stride) {
+        double2 wi = w2[i];
         if (OP == 0) {
 #pragma unroll
-            for (int k = 0; k < KMAX; ++k)
-                if (k < nv) acc[k] += V[k * ld + i] * wi;
+            for (int k = 0; k < NV; ++k)
+                if (k < nv) {
+                    double2 v = V2[k * ld2 + i];
+                    acc[k] += v.x * wi.x + v.y * wi.y;
+                }
         } else if (OP == 1) {
-            double v[KMAX];
+            double2 v[NV];
 #pragma unroll
-            for (int k = 0; k < KMAX; ++k) v[k] = k < nv ? V[k * ld + i] : 0.0;
+            for (int k = 0; k < NV; ++k) v[k] = k < nv ? V2[k * ld2 + i] : make_double2(0.0, 0.0);
 #pragma unroll
-            for (int k = 0; k < KMAX; ++k)
-                if (k < nv) wi -= hh[k] * v[k];
-            w[i] = wi;
+            for (int k = 0; k < NV; ++k)
+                if (k < nv) {
+                    wi.x -= hh[k] * v[k].x;
+                    wi.y -= hh[k] * v[k].y;
+                }
+            w2[i] = wi;
 #pragma unroll
-            for (int k = 0; k < KMAX; ++k)
-                if (k < nv) acc[k] += v[k] * wi;
+            for (int k = 0; k < NV; ++k)
+                if (k < nv) acc[k] += v[k].x * wi.x + v[k].y * wi.y;
         } else if (OP == 2) {
 #pragma unroll
-            for (int k = 0; k < KMAX; ++k)
-                if (k < nv) wi -= hh[k] * V[k * ld + i];
-            w[i] = wi;
-            acc[0] += wi * wi;
+            for (int k = 0; k < NV; ++k)
+                if (k < nv) {
+                    double2 v = V2[k * ld2 + i];
+                    wi.x -= hh[k] * v.x;
+                    wi.y -= hh[k] * v.y;
+                }
+            w2[i] = wi;
+            acc[0] += wi.x * wi.x + wi.y * wi.y;
         } else {
-            acc[0] += wi * wi;
+            acc[0] += wi.x * wi.x + wi.y * wi.y;
         }
     }
     const int nres = (OP == 0 || OP == 1) ? nv : 1;
+    const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
 #pragma unroll
-    for (int k = 0; k < KMAX; ++k) {
+    for (int k = 0; k < NV; ++k) {
         if (k < nres) {
-            double s = block_sum(acc[k], sh);
-            if (threadIdx.x == 0) part[(int64_t)blockIdx.x * KMAX + k] = s;
+            double v = wave_sum(acc[k]);
+            if (lane == 0) sh[k][wv] = v;
         }
     }
-    if (threadIdx.x == 0) {
+    __syncthreads();
+    if ((int)threadIdx.x < nres) {
+        double b = 0.0;
+#pragma unroll
+        for (int q = 0; q < RBLK / WAVE; ++q) b += sh[threadIdx.x][q];
+        part[(int64_t)blockIdx.x * KMAX + threadIdx.x] = b;
         __threadfence();
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
         unsigned int ticket = atomicAdd(count, 1u);
         last = (ticket == gridDim.x - 1);
     }
     __syncthreads();
     if (!last) return;
     __threadfence();
-    for (int k = 0; k < nres; ++k) {
+    // last block: wave wv sums result k = wv, wv + 4, ... over the blocks
+    for (int k = wv; k < nres; k += RBLK / WAVE) {
         double v = 0.0;
-        for (int b = threadIdx.x; b < (int)gridDim.x; b += RBLK) v += part[(int64_t)b * KMAX + k];
-        double s = block_sum(v, sh);
-        if (threadIdx.x == 0) out[k] = s;
+        for (int b = lane; b < (int)gridDim.x; b += WAVE) v += part[(int64_t)b * KMAX + k];
+        v = wave_sum(v);
+        if (lane == 0) out[k] = v;
     }
     if (threadIdx.x == 0) *count = 0u;
 }
 
 static int red_grid(int64_t len) {
-    int64_t g = (len + RBLK * 4 - 1) / (RBLK * 4);
+    int64_t g = (len / 2 + RBLK * 4 - 1) / (RBLK * 4);
     if (g < 1) g = 1;
     if (g > MAX_RED_BLOCKS) g = MAX_RED_BLOCKS;
     return (int)g;
+}
+
+template <int OP, int NV>
+static void red_go(dp_sim* s, int g, const double* V, int64_t ld, int nv, const double* h, double* w,
+                   int64_t len, double* out) {
+    red_kernel<OP, NV><<<g, RBLK, 0, s->stream>>>(V, ld, nv, h, w, len, s->red_part, s->red_count, out);
 }
 
 template <int OP>
 static void red_launch(dp_sim* s, const double* V, int64_t ld, int nv, const double* h, double* w,
                        int64_t len, double* out) {
     if (nv > KMAX) fail(DP_E_INVALID, "too many Krylov vectors");
+    if ((len & 1) || (ld & 1)) fail(DP_E_INVALID, "Krylov vectors must have even length");
     int g = red_grid(len);
-    red_kernel<OP><<<g, RBLK, 0, s->stream>>>(V, ld, nv, h, w, len, s->red_part, s->red_count, out);
+    if (g > s->red_blocks) fail(DP_E_INVALID, "reduction buffer too small");
+    if constexpr (OP == 3) {
+        red_go<OP, 1>(s, g, V, ld, nv, h, w, len, out);
+    } else if (nv <= 2) {
+        red_go<OP, 2>(s, g, V, ld, nv, h, w, len, out);
+    } else if (nv <= 4) {
+        red_go<OP, 4>(s, g, V, ld, nv, h, w, len, out);
+    } else if (nv <= 8) {
+        red_go<OP, 8>(s, g, V, ld, nv, h, w, len, out);
+    } else if (nv <= 16) {
+        red_go<OP, 16>(s, g, V, ld, nv, h, w, len, out);
+    } else {
+        red_go<OP, KMAX>(s, g, V, ld, nv, h, w, len, out);
+    }
     DP_LAUNCH_CHECK();
 }
 

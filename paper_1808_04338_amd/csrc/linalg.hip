@@ -417,38 +417,56 @@ __global__ void ilu_black_kernel(IluArgs<T> a) {
     if (p >= 0) stb(a.F.ubw0, a.F.ubw1, p, ubw);
 }
 
-// well rows: one thread per well, perforations in elimination order
+// well rows: one wavefront per well.  The well row's entries are eliminated in
+// elimination order: first every even (red) perforation, l_p = A_wp U_pp^-1,
+// which fills the well row at the odd perforations of the same well that
+// couple to it; then every odd (black) perforation, whose entry gathers that
+// fill (A_wp - sum l_r U_rp over its even neighbours perforated by the same
+// well) before l_p = (.) U_pp^-1.  U_ww = A_ww - sum_p l_p U_pw, summed per
+// lane and then across the wave in a fixed order.
 template <class T>
-__global__ void ilu_well_kernel(IluArgs<T> a) {
-    int w = blockIdx.x * blockDim.x + threadIdx.x;
-    if (w >= a.nw) return;
+__global__ void __launch_bounds__(WAVE) ilu_well_kernel(IluArgs<T> a) {
+    int w = blockIdx.x;
+    int lane = threadIdx.x;
     int n = a.n;
     int p0 = a.well_ptr[w], p1 = a.well_ptr[w + 1];
-    for (int p = p0; p < p1; ++p) stb(a.F.lw0, a.F.lw1, p, ldb(a.A.wf0, a.A.wf1, p));
-    Blk<T> dw = ldb(a.A.d0, a.A.d1, 2 * n + w);
-    for (int pass = 0; pass < 2; ++pass) {
-        for (int p = p0; p < p1; ++p) {
-            int q = a.perf_q[p];
-            bool red = q < a.nred;
-            if (red != (pass == 0)) continue;
-            Blk<T> l = bmm(ldb(a.F.lw0, a.F.lw1, p), ldb(a.F.ui0, a.F.ui1, n + q));
-            stb(a.F.lw0, a.F.lw1, p, l);
-            if (red) {
-                unsigned mask = a.fmask[q];
-                for (int s = 0; s < 6; ++s) {
-                    if (!(mask & (1u << s))) continue;
-                    int bq = a.fcol[s * n + q] - n;
-                    int pb = a.fperf[bq];
-                    if (pb >= 0 && a.perf_well[pb] == w) {
-                        Blk<T> u = ldb(a.A.f0, a.A.f1, (int64_t)s * n + q);
-                        stb(a.F.lw0, a.F.lw1, pb, bsub(ldb(a.F.lw0, a.F.lw1, pb), bmm(l, u)));
-                    }
-                }
-            }
-            dw = bsub(dw, bmm(l, ldb(a.F.ubw0, a.F.ubw1, p)));
-        }
+    Blk<T> acc = {0, 0, 0, 0};
+    for (int p = p0 + lane; p < p1; p += WAVE) {
+        int q = a.perf_q[p];
+        if (q >= a.nred) continue;
+        Blk<T> l = bmm(ldb(a.A.wf0, a.A.wf1, p), ldb(a.F.ui0, a.F.ui1, n + q));
+        stb(a.F.lw0, a.F.lw1, p, l);
+        Blk<T> t = bmm(l, ldb(a.F.ubw0, a.F.ubw1, p));
+        acc = badd(acc, t);
     }
-    stb(a.F.ui0, a.F.ui1, 2 * n + w, binv(dw));
+    __syncthreads();  // the even perforations' l_p are visible to the whole wave
+    for (int p = p0 + lane; p < p1; p += WAVE) {
+        int q = a.perf_q[p];
+        if (q < a.nred) continue;
+        Blk<T> lw = ldb(a.A.wf0, a.A.wf1, p);
+        unsigned mask = a.fmask[q];
+        for (int s = 0; s < 6; ++s) {
+            if (!(mask & (1u << s))) continue;
+            int rq = a.fcol[s * n + q] - n;
+            int pr = a.fperf[rq];
+            if (rq < a.nred && pr >= 0 && a.perf_well[pr] == w) {
+                // the even row's block pointing back at this row sits in the opposite slot
+                Blk<T> u = ldb(a.A.f0, a.A.f1, (int64_t)(s ^ 1) * n + rq);
+                lw = bsub(lw, bmm(ldb(a.F.lw0, a.F.lw1, pr), u));
+            }
+        }
+        Blk<T> l = bmm(lw, ldb(a.F.ui0, a.F.ui1, n + q));
+        stb(a.F.lw0, a.F.lw1, p, l);
+        acc = badd(acc, bmm(l, ldb(a.F.ubw0, a.F.ubw1, p)));
+    }
+    acc.a00 = wave_sum(acc.a00);
+    acc.a01 = wave_sum(acc.a01);
+    acc.a10 = wave_sum(acc.a10);
+    acc.a11 = wave_sum(acc.a11);
+    if (lane == 0) {
+        Blk<T> dw = bsub(ldb(a.A.d0, a.A.d1, 2 * n + w), acc);
+        stb(a.F.ui0, a.F.ui1, 2 * n + w, binv(dw));
+    }
 }
 
 template <class T>
@@ -485,7 +503,7 @@ void ilu_factor(dp_sim* s) {
     DP_LAUNCH_CHECK();
     if (t.n - t.nred > 0) ilu_black_kernel<T><<<ceil_div(t.n - t.nred, 256), 256, 0, s->stream>>>(a);
     DP_LAUNCH_CHECK();
-    if (t.nw > 0) ilu_well_kernel<T><<<ceil_div(t.nw, 64), 64, 0, s->stream>>>(a);
+    if (t.nw > 0) ilu_well_kernel<T><<<t.nw, WAVE, 0, s->stream>>>(a);
     DP_LAUNCH_CHECK();
 }
 template void ilu_factor<double>(dp_sim*);

@@ -16,7 +16,7 @@ namespace dp {
 // Galerkin products per level-0 pressure nonzero that the setup scratch is
 // sized for: the worst case trunc^2 with at most four interpolation entries.
 constexpr double RAP_EXPANSION = 16.0;
-constexpr int MAX_RED_BLOCKS_ALL = 1024;
+constexpr int MAX_RED_BLOCKS_ALL = 2048;
 
 static void fill_defaults(dp_sim_desc& d) {
     if (d.gmres_restart <= 0) d.gmres_restart = 30;
