@@ -103,8 +103,10 @@ def timed_form(model, precision, steps, warmup, rtol, state=None, kernels=True, 
     sim.enable_timing(False)
     kern = sim.bench_kernels(20) if kernels else []
     levels = sim.amg_info()
+    global_sorts = sim.amg_global_sort_products()
     out = dict(wall=wall, lat=lat, iters=its_l, rel=rel, phases=phases, kern=kern,
                amg_rows=[int(r) for r in levels[1]], amg_nnz=[int(r) for r in levels[2]],
+               amg_global_sorts=global_sorts,
                footprint=sim.footprint, n_dof=sim.n_dof, nnz=sim.nnz)
     sim.close()
     return out, state
@@ -225,6 +227,8 @@ def main():
         "gmres_iters": r32["iters"],
         "phases_ms": r32["phases"],
         "amg_rows": r32["amg_rows"],
+        "amg_nnz": r32["amg_nnz"],
+        "amg_global_sort_products": r32["amg_global_sorts"],
         "roofline": roof,
         "kernels": r32["kern"],
         "cpu_baseline": cpu,

@@ -207,6 +207,11 @@ dp_status sim_export_ilu(dp_sim *sim, int32_t *perm, int32_t *brow, int32_t *bco
 /* AMG hierarchy sizes: levels, rows[l], nnz[l] (arrays of amg_max_levels). */
 dp_status sim_amg_info(dp_sim *sim, int32_t *levels, int32_t *rows, int64_t *nnz);
 
+/* Setup statistics since sim_create: the number of AMG products (interpolation
+ * or Galerkin, one per level and setup) that had a row too long for the
+ * row-wise LDS path and were formed by the global sort path instead. */
+dp_status sim_amg_stats(dp_sim *sim, int64_t *global_sort_products);
+
 /* Level l: splitting cf[rows[l]] (1 = C, -1 = F; not for the coarsest), the
  * operator A_l in CSR, and for l < levels-1 the interpolation P_l in CSR.
  * Level 0 is the pressure system with the matrix-node pressures eliminated

@@ -86,6 +86,7 @@ _SIGS = {
     "sim_export_system": [C.c_void_p, C.c_int32, _iptr, _iptr, _dptr, _dptr],
     "sim_export_ilu": [C.c_void_p, _iptr, _iptr, _iptr, _dptr],
     "sim_amg_info": [C.c_void_p, _iptr, _iptr, _lptr],
+    "sim_amg_stats": [C.c_void_p, _lptr],
     "sim_export_amg_level": [C.c_void_p, C.c_int32, _iptr, _iptr, _iptr, _dptr, _iptr, _iptr, _dptr,
                              _lptr],
     "sim_apply_precond": [C.c_void_p, _dptr, _dptr],

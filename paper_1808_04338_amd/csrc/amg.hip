@@ -245,6 +245,45 @@ __global__ void interp_expand_e(Csr A, const int* __restrict__ erow, const unsig
     }
 }
 
+// The same interpolation terms as column/value pairs (the segmented path):
+// terms of F row i are contiguous because A's entries are grouped by row.
+__global__ void interp_expand_c(Csr A, const int* __restrict__ erow, const unsigned char* __restrict__ smask,
+                                const int* __restrict__ cf, const int64_t* __restrict__ cidx,
+                                const double* __restrict__ diag, const double* __restrict__ beta,
+                                const int64_t* __restrict__ off, int* cols, double* vals) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= A.nnz) return;
+    int i = erow[e];
+    int j = A.col[e];
+    if (cf[i] > 0 || j == i || !smask[e]) return;
+    int64_t o = off[e];
+    double a = A.val[e];
+    if (cf[j] > 0) {
+        cols[o] = (int)cidx[j];
+        vals[o] = a;
+    } else if (beta[j] != 0.0) {
+        double bk = beta[j], dk = diag[j];
+        for (int f = A.rowptr[j]; f < A.rowptr[j + 1]; ++f) {
+            int jj = A.col[f];
+            double v = A.val[f];
+            if (smask[f] && cf[jj] > 0 && v * dk < 0.0) {
+                cols[o] = (int)cidx[jj];
+                vals[o] = a * (v / bk);
+                ++o;
+            }
+        }
+    }
+}
+
+// Row offsets of terms generated per matrix entry: row r starts where its first
+// entry's terms start (eoff: exclusive scan over the nnz entries, total m).
+__global__ void seg_off_from_entries(const int* __restrict__ rowptr, const int64_t* __restrict__ eoff, int n,
+                                     int64_t nnz, int64_t m, int64_t* seg) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) seg[i] = rowptr[i] < nnz ? eoff[rowptr[i]] : m;
+    if (i == n) seg[n] = m;
+}
+
 constexpr int TRUNC_MAX = 8;
 
 // Selection of the kept entries of one F row: the 'trunc' largest |w|
@@ -872,26 +911,43 @@ void amg_setup(dp_sim* s) {
             DP_LAUNCH_CHECK();
             int64_t m = 0;
             exclusive_scan(st, ecnt, A.nnz, etmp, &m);
-            int cbits = bits_for(nc);
-            int rbits = bits_for(n);
-            uint64_t* k0 = Sc.get<uint64_t>(m, "interp keys");
-            double* v0 = Sc.get<double>(m, "interp vals");
-            uint64_t* k1 = Sc.get<uint64_t>(m, "interp keys");
-            double* v1 = Sc.get<double>(m, "interp vals");
-            int64_t* rtmp = Sc.get<int64_t>(sort_tmp_size(m), "sort tmp");
-            interp_expand_e<<<ceil_div(A.nnz, 256), 256, 0, st>>>(A, erow, smask, L.cf, cidx, diag, beta,
-                                                                  ecnt, cbits, k0, v0);
-            DP_LAUNCH_CHECK();
-            int which = radix_sort(st, k0, v0, k1, v1, m, rbits + cbits, rtmp);
-            uint64_t* ks = which ? k1 : k0;
-            double* vs = which ? v1 : v0;
-            // the idle half of the sort's double buffer holds the run flags and sums
-            int64_t* flag = (int64_t*)(which ? k0 : k1);
-            double* sums = which ? v0 : v1;
-            int* rowkey = Sc.get<int>(m, "rbk rows");
             Csr W;
             W.ncols = nc;
-            reduce_to_csr(st, ks, vs, m, cbits, n, flag, sums, rowkey, rtmp, Sc, W, "interp W");
+            // segmented path: terms are already grouped by F row
+            bool done = false;
+            {
+                size_t wmark = Sc.top;
+                int* wc = Sc.get<int>(m, "interp terms");
+                double* wv = Sc.get<double>(m, "interp terms");
+                int64_t* woff = Sc.get<int64_t>(n + 1, "interp rows");
+                interp_expand_c<<<ceil_div(A.nnz, 256), 256, 0, st>>>(A, erow, smask, L.cf, cidx, diag, beta,
+                                                                      ecnt, wc, wv);
+                seg_off_from_entries<<<ceil_div(n + 1, 256), 256, 0, st>>>(A.rowptr, ecnt, n, A.nnz, m, woff);
+                DP_LAUNCH_CHECK();
+                done = seg_sort_reduce(st, woff, n, nc, wc, wv, m, Sc, Sc, W, "interp W");
+                if (!done) Sc.top = wmark;
+            }
+            if (!done) {
+                int cbits = bits_for(nc);
+                int rbits = bits_for(n);
+                uint64_t* k0 = Sc.get<uint64_t>(m, "interp keys");
+                double* v0 = Sc.get<double>(m, "interp vals");
+                uint64_t* k1 = Sc.get<uint64_t>(m, "interp keys");
+                double* v1 = Sc.get<double>(m, "interp vals");
+                int64_t* rtmp = Sc.get<int64_t>(sort_tmp_size(m), "sort tmp");
+                interp_expand_e<<<ceil_div(A.nnz, 256), 256, 0, st>>>(A, erow, smask, L.cf, cidx, diag, beta,
+                                                                      ecnt, cbits, k0, v0);
+                DP_LAUNCH_CHECK();
+                int which = radix_sort(st, k0, v0, k1, v1, m, rbits + cbits, rtmp);
+                uint64_t* ks = which ? k1 : k0;
+                double* vs = which ? v1 : v0;
+                // the idle half of the sort's double buffer holds the run flags and sums
+                int64_t* flag = (int64_t*)(which ? k0 : k1);
+                double* sums = which ? v0 : v1;
+                int* rowkey = Sc.get<int>(m, "rbk rows");
+                reduce_to_csr(st, ks, vs, m, cbits, n, flag, sums, rowkey, rtmp, Sc, W, "interp W");
+                s->seg_fallbacks += 1;
+            }
             // truncation into P
             int64_t* pc = Sc.get<int64_t>(n + 1, "P count");
             pcount_kernel<<<ceil_div(n, 256), 256, 0, st>>>(W, L.cf, dd, d.amg_trunc, pc);
@@ -932,9 +988,17 @@ void amg_setup(dp_sim* s) {
                           H, R, "R");
         }
         Sc.top = smark;
-        // Galerkin A_c = R A P
+        // Galerkin A_c = R (A P), both products row by row
         Csr Ac;
+        Ac.ncols = nc;
+        bool rap_done = false;
         {
+            Csr AP;
+            if (seg_product(st, A, L.P, Sc, Sc, AP, "A P")) rap_done = seg_product(st, R, AP, Sc, H, Ac, "coarse A");
+            Sc.top = smark;
+        }
+        if (!rap_done) {
+            s->seg_fallbacks += 1;
             int* erow = Sc.get<int>(A.nnz, "entry rows");
             int64_t* cnt = Sc.get<int64_t>(A.nnz + 1, "rap count");
             int64_t* stmp = Sc.get<int64_t>(scan_tmp_size(A.nnz + 1), "scan tmp");
@@ -955,7 +1019,6 @@ void amg_setup(dp_sim* s) {
             int64_t* flag = (int64_t*)(which ? k0 : k1);
             double* sums = which ? v0 : v1;
             int* rowkey = Sc.get<int>(m, "rbk rows");
-            Ac.ncols = nc;
             reduce_to_csr(st, which ? k1 : k0, which ? v1 : v0, m, cb, nc, flag, sums, rowkey, rtmp, H,
                           Ac, "coarse A");
         }

@@ -23,6 +23,23 @@ int64_t reduce_to_csr(hipStream_t st, const uint64_t* k, const double* v, int64_
                       int nrows, int64_t* flag, double* sums, int* rowkey, int64_t* tmp, Arena& out,
                       Csr& csr, const char* what);
 
+// Segmented sort-and-reduce into CSR: row r's terms (col[e], val[e]) for e in
+// [off[r], off[r+1]) (off: nrows + 1 entries, m = off[nrows]) are ordered by
+// column, ties in term order; equal columns are summed in term order and zero
+// sums dropped.  col/val are overwritten.  The CSR arrays come from 'out',
+// temporaries from 'sc' (released unless out is sc).  Returns false, with
+// nothing allocated from 'out', when a row holds more terms than one workgroup
+// sorts in LDS (4096); the caller then takes the global sort path.
+bool seg_sort_reduce(hipStream_t st, const int64_t* off, int nrows, int ncols, int* col, double* val,
+                     int64_t m, Arena& sc, Arena& out, Csr& csr, const char* what);
+
+// C = X Y row by row (terms of row r: X_re Y_ef for the entries e of X's row r
+// and f of Y's row e, summed per column in that order, zero sums dropped).  C
+// comes from 'out', temporaries from 'sc'.  Returns false, with nothing
+// allocated from 'out', when a row of C has more terms than one workgroup
+// sorts in LDS; the caller then takes the global sort path.
+bool seg_product(hipStream_t st, const Csr& X, const Csr& Y, Arena& sc, Arena& out, Csr& C, const char* what);
+
 inline int bits_for(int64_t n) {
     int b = 1;
     while ((int64_t(1) << b) < n) ++b;

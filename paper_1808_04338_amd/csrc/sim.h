@@ -165,6 +165,7 @@ struct dp_sim {
     double red_host[256] = {};    // host copy of reduction results
     unsigned int* red_count = nullptr;
     int red_blocks = 0;
+    int64_t seg_fallbacks = 0;  // AMG products that took the global sort path
 
     // sort / setup scratch (part of the per-setup region)
     size_t scratch_bytes = 0;

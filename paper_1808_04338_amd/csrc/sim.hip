@@ -1147,6 +1147,12 @@ dp_status sim_amg_info(dp_sim* sim, int32_t* levels, int32_t* rows, int64_t* nnz
     return DP_OK;
 }
 
+dp_status sim_amg_stats(dp_sim* sim, int64_t* global_sort_products) {
+    if (!sim) return DP_E_INVALID;
+    if (global_sort_products) *global_sort_products = sim->seg_fallbacks;
+    return DP_OK;
+}
+
 dp_status sim_export_amg_level(dp_sim* sim, int32_t level, int32_t* cf, int32_t* a_rowptr, int32_t* a_col,
                                double* a_val, int32_t* p_rowptr, int32_t* p_col, double* p_val,
                                int64_t* p_nnz) {

@@ -207,6 +207,12 @@ class Sim:
         self._chk(self.lib.sim_amg_info(self.h, C.byref(nl), _ip(rows), _lp(nnz)))
         return nl.value, rows[:nl.value].copy(), nnz[:nl.value].copy()
 
+    def amg_global_sort_products(self):
+        """AMG products (one per level and setup) formed by the global sort path."""
+        v = C.c_int64()
+        self._chk(self.lib.sim_amg_stats(self.h, C.byref(v)))
+        return v.value
+
     def export_amg_level(self, level):
         nl, rows, nnz = self.amg_info()
         n = int(rows[level])

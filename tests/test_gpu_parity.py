@@ -88,10 +88,14 @@ def test_decoupling_and_ilu_match_oracle(name):
     sim.close()
 
 
-def test_amg_hierarchy_matches_oracle():
+@pytest.mark.parametrize("name", ["medium", "tall_well"])
+def test_amg_hierarchy_matches_oracle(name):
     """Identical C/F splittings at every level (a deterministic rule), P and the
-    Galerkin operators to 1e-10, on the 144k-DOF model."""
-    m = synth.model_layered()
+    Galerkin operators to 1e-10: on the 144k-DOF model, and on a 6x6x900 model
+    whose two wells perforate 900 layers, so that Galerkin rows of every length
+    class occur (wavefront tiles, workgroup tiles and rows beyond the LDS tiles,
+    which take the global sort path)."""
+    m = synth.model_layered() if name == "medium" else synth.model_tiny(6, 6, 900, seed=6)
     x, x_old = random_state_pair(m, 5)
     dt = 5 * synth.DAY
     geo, R, J = oracle_system(m, x, x_old, dt)
@@ -109,6 +113,8 @@ def test_amg_hierarchy_matches_oracle():
             assert np.array_equal(g["cf"], o["state"])
             assert sparse_rel(g["P"], o["P"]) <= 1e-10
             assert g["P"].nnz == o["P"].nnz
+    if name == "tall_well":
+        assert sim.amg_global_sort_products() >= 1
     # the V-cycle on the reduced pressure system
     rr = np.random.default_rng(2).standard_normal(rows[0])
     e = sim.apply_stage(1, rr)
