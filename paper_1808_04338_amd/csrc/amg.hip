@@ -62,24 +62,48 @@ void amg_extract_level0(dp_sim* s) {
 // Strength: j strongly influences i if -a_ij sgn(a_ii) >= theta max_k(-a_ik sgn(a_ii))
 // and that maximum is > 0.  Also |S^T_i| (integer atomics) and the diagonal.
 // ---------------------------------------------------------------------------
+// Row kernels below give each row RL consecutive lanes (a subgroup); the
+// subgroup reductions use xor shuffles of width RL.
+constexpr int RL = 8;
+
+__device__ inline double rl_sum(double v) {
+#pragma unroll
+    for (int o = RL / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, RL);
+    return v;
+}
+__device__ inline double rl_max(double v) {
+#pragma unroll
+    for (int o = RL / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, RL));
+    return v;
+}
+__device__ inline int rl_or(int v) {
+#pragma unroll
+    for (int o = RL / 2; o > 0; o >>= 1) v |= __shfl_xor(v, o, RL);
+    return v;
+}
+inline int rl_grid(int n) { return ceil_div((int64_t)n * RL, 256); }
+
 __global__ void strength_kernel(Csr A, double theta, unsigned char* smask, int* nst, double* diag) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= A.n) return;
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    int i = g / RL, l = g % RL;
+    if (i >= A.n) return;  // whole subgroup
     int b = A.rowptr[i], e1 = A.rowptr[i + 1];
     double d = 0.0;
-    for (int e = b; e < e1; ++e)
+    for (int e = b + l; e < e1; e += RL)
         if (A.col[e] == i) d = A.val[e];
-    diag[i] = d;
+    d = rl_sum(d);  // one lane holds the diagonal
     double sg = d < 0.0 ? -1.0 : 1.0;
     double mx = -INFINITY;
-    for (int e = b; e < e1; ++e)
+    for (int e = b + l; e < e1; e += RL)
         if (A.col[e] != i) mx = fmax(mx, -A.val[e] * sg);
-    for (int e = b; e < e1; ++e) {
+    mx = rl_max(mx);
+    for (int e = b + l; e < e1; e += RL) {
         int j = A.col[e];
         bool st = (j != i) && (mx > 0.0) && (-A.val[e] * sg >= theta * mx);
         smask[e] = st ? 1 : 0;
         if (st) atomicAdd(&nst[j], 1);
     }
+    if (l == 0) diag[i] = d;
 }
 
 // lowbias32 integer hash (C. Wellons)
@@ -91,6 +115,8 @@ __device__ inline uint32_t lowbias32(uint32_t x) {
     x ^= x >> 16;
     return x;
 }
+
+constexpr int PMIS_BATCH = 4;  // PMIS iterations between termination checks
 
 __global__ void pmis_init(int n, const int* __restrict__ nst, int* state, double* wgt) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -127,12 +153,17 @@ __global__ void pmis_select(int n, int* state, const int* __restrict__ beaten, i
 __global__ void pmis_fpass(Csr A, const unsigned char* __restrict__ smask, int* state, int iter,
                            int* undecided) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= A.n || state[i] != ST_U) return;
-    bool f = false;
-    for (int e = A.rowptr[i]; e < A.rowptr[i + 1]; ++e)
-        if (smask[e] && state[A.col[e]] == C_BASE + iter) f = true;
-    if (f) state[i] = ST_F;
-    else atomicAdd(undecided, 1);
+    bool und = false;
+    if (i < A.n && state[i] == ST_U) {
+        bool f = false;
+        for (int e = A.rowptr[i]; e < A.rowptr[i + 1]; ++e)
+            if (smask[e] && state[A.col[e]] == C_BASE + iter) f = true;
+        if (f) state[i] = ST_F;
+        else und = true;
+    }
+    // one atomic per wavefront
+    uint64_t m = __ballot(und);
+    if (threadIdx.x % WAVE == 0 && m) atomicAdd(undecided, (int)__popcll(m));
 }
 
 __global__ void pmis_final(int n, const int* __restrict__ state, int* cf, int64_t* cflag) {
@@ -173,9 +204,10 @@ __global__ void interp_beta(Csr A, const unsigned char* __restrict__ smask, cons
 
 // Row of every stored entry (thread per row).
 __global__ void entry_rows(Csr A, int* erow) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    int i = g / RL, l = g % RL;
     if (i >= A.n) return;
-    for (int e = A.rowptr[i]; e < A.rowptr[i + 1]; ++e) erow[e] = i;
+    for (int e = A.rowptr[i] + l; e < A.rowptr[i + 1]; e += RL) erow[e] = i;
 }
 
 // d_i of every F row: diagonal + weak entries + strong F entries whose row
@@ -427,12 +459,19 @@ __global__ void rap_expand_e(Csr A, const int* __restrict__ erow, Csr P, const i
 // ---------------------------------------------------------------------------
 // SELL-64 conversion and the l1-Jacobi diagonal
 // ---------------------------------------------------------------------------
-__global__ void sell_width(Csr A, int nslices, int64_t* w) {
+// Slice widths (w[nslices] = 0, so that the exclusive scan leaves the total
+// there) and the longest row (atomic max into *maxw).
+__global__ void sell_width(Csr A, int nslices, int64_t* w, int* maxw) {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= nslices) return;
+    if (s > nslices) return;
+    if (s == nslices) {
+        w[s] = 0;
+        return;
+    }
     int mx = 0;
     for (int r = s * 64; r < s * 64 + 64 && r < A.n; ++r) mx = max(mx, A.rowptr[r + 1] - A.rowptr[r]);
     w[s] = (int64_t)mx * 64;
+    atomicMax(maxw, mx);
 }
 
 __global__ void sell_ptr(const int64_t* __restrict__ off, int nslices, int64_t total, int* sptr) {
@@ -467,16 +506,18 @@ __global__ void sell_fill(Csr A, const int* __restrict__ sptr, int pad_self, int
 
 template <class T>
 __global__ void l1_kernel(Csr A, T* dinv) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    int i = g / RL, l = g % RL;
     if (i >= A.n) return;
     double d = 0.0, s = 0.0;
-    for (int e = A.rowptr[i]; e < A.rowptr[i + 1]; ++e) {
+    for (int e = A.rowptr[i] + l; e < A.rowptr[i + 1]; e += RL) {
         if (A.col[e] == i) d = A.val[e];
+        else s += fabs(A.val[e]);
     }
-    for (int e = A.rowptr[i]; e < A.rowptr[i + 1]; ++e)
-        if (A.col[e] != i) s += fabs(A.val[e]);
+    d = rl_sum(d);
+    s = rl_sum(s);
     double sg = d < 0.0 ? -1.0 : 1.0;
-    dinv[i] = (T)(1.0 / (d + sg * s));
+    if (l == 0) dinv[i] = (T)(1.0 / (d + sg * s));
 }
 
 __global__ void i64_to_i32(const int64_t* __restrict__ a, int n, int64_t total, int* b) {
@@ -735,18 +776,23 @@ static void build_op(dp_sim* s, const Csr& A, Op& op, bool pad_self, Arena& H, A
     op.nnz = A.nnz;
     int nsl = (A.n + 63) / 64;
     size_t mark = Sc.top;
-    int64_t* w = Sc.get<int64_t>(nsl + 1, "sell widths");
-    int64_t* tmp = Sc.get<int64_t>(scan_tmp_size(nsl + 1), "sell scan");
+    int64_t* w = Sc.get<int64_t>(nsl + 2, "sell widths");
+    int64_t* tmp = Sc.get<int64_t>(scan_tmp_size(nsl + 2), "sell scan");
+    int* dmax = Sc.get<int>(1, "sell width");
     int64_t total = 0;
     int64_t maxw = 0;
     if (nsl > 0) {
-        sell_width<<<ceil_div(nsl, 256), 256, 0, st>>>(A, nsl, w);
+        DP_HIP(hipMemsetAsync(dmax, 0, sizeof(int), st));
+        sell_width<<<ceil_div(nsl + 1, 256), 256, 0, st>>>(A, nsl, w, dmax);
         DP_LAUNCH_CHECK();
-        std::vector<int64_t> hw(nsl);
-        DP_HIP(hipMemcpyAsync(hw.data(), w, sizeof(int64_t) * nsl, hipMemcpyDeviceToHost, st));
+        scan_inplace(st, w, nsl + 1, tmp);
+        int64_t h[2] = {0, 0};
+        DP_HIP(hipMemcpyAsync(&h[0], w + nsl, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        int hm = 0;
+        DP_HIP(hipMemcpyAsync(&hm, dmax, sizeof(int), hipMemcpyDeviceToHost, st));
         DP_HIP(hipStreamSynchronize(st));
-        for (int64_t x : hw) maxw = std::max(maxw, x / 64);
-        exclusive_scan(st, w, nsl, tmp, &total);
+        total = h[0];
+        maxw = hm;
     }
     bool sell = total <= (int64_t)(1.3 * (double)A.nnz) + 64 && maxw <= 48;
     size_t es = s->fp32 ? sizeof(float) : sizeof(double);
@@ -794,8 +840,8 @@ static void level_apply_data(dp_sim* s, AmgLevel& L, Arena& H, Arena& Sc) {
     L.r = H.take(es * (L.n > 0 ? L.n : 1), "amg r");
     L.t = H.take(es * (L.n > 0 ? L.n : 1), "amg t");
     if (L.n == 0) return;
-    if (s->fp32) l1_kernel<float><<<ceil_div(L.n, 256), 256, 0, s->stream>>>(L.A, (float*)L.dinv);
-    else l1_kernel<double><<<ceil_div(L.n, 256), 256, 0, s->stream>>>(L.A, (double*)L.dinv);
+    if (s->fp32) l1_kernel<float><<<rl_grid(L.n), 256, 0, s->stream>>>(L.A, (float*)L.dinv);
+    else l1_kernel<double><<<rl_grid(L.n), 256, 0, s->stream>>>(L.A, (double*)L.dinv);
     DP_LAUNCH_CHECK();
 }
 
@@ -860,24 +906,28 @@ void amg_setup(dp_sim* s) {
             int* state = Sc.get<int>(n, "pmis state");
             double* wgt = Sc.get<double>(n, "pmis weight");
             int* beaten = Sc.get<int>(n, "pmis beaten");
-            int* und = Sc.get<int>(1, "pmis count");
+            int* und = Sc.get<int>(PMIS_BATCH, "pmis count");
             cidx = Sc.get<int64_t>(n + 1, "coarse index");
             int64_t* stmp = Sc.get<int64_t>(scan_tmp_size(n + 1), "scan tmp");
             L.cf = H.get<int>(n, "cf");
             DP_HIP(hipMemsetAsync(nst, 0, sizeof(int) * n, st));
             DP_HIP(hipMemsetAsync(beaten, 0xff, sizeof(int) * n, st));
-            strength_kernel<<<ceil_div(n, 256), 256, 0, st>>>(A, d.amg_theta, smask, nst, diag);
+            strength_kernel<<<rl_grid(n), 256, 0, st>>>(A, d.amg_theta, smask, nst, diag);
             pmis_init<<<ceil_div(n, 256), 256, 0, st>>>(n, nst, state, wgt);
             DP_LAUNCH_CHECK();
-            for (int iter = 0;; ++iter) {
+            // iterations in batches: once no point is undecided an iteration
+            // changes nothing, so only the last count of a batch is checked
+            for (int iter = 0;;) {
                 if (iter > 10000) fail(DP_E_NUMERIC, "PMIS did not terminate");
-                DP_HIP(hipMemsetAsync(und, 0, sizeof(int), st));
-                pmis_beat<<<ceil_div(n, 256), 256, 0, st>>>(A, smask, state, wgt, iter, beaten);
-                pmis_select<<<ceil_div(n, 256), 256, 0, st>>>(n, state, beaten, iter);
-                pmis_fpass<<<ceil_div(n, 256), 256, 0, st>>>(A, smask, state, iter, und);
+                DP_HIP(hipMemsetAsync(und, 0, sizeof(int) * PMIS_BATCH, st));
+                for (int b = 0; b < PMIS_BATCH; ++b, ++iter) {
+                    pmis_beat<<<ceil_div(n, 256), 256, 0, st>>>(A, smask, state, wgt, iter, beaten);
+                    pmis_select<<<ceil_div(n, 256), 256, 0, st>>>(n, state, beaten, iter);
+                    pmis_fpass<<<ceil_div(n, 256), 256, 0, st>>>(A, smask, state, iter, und + b);
+                }
                 DP_LAUNCH_CHECK();
                 int hu = 0;
-                DP_HIP(hipMemcpyAsync(&hu, und, sizeof(int), hipMemcpyDeviceToHost, st));
+                DP_HIP(hipMemcpyAsync(&hu, und + PMIS_BATCH - 1, sizeof(int), hipMemcpyDeviceToHost, st));
                 DP_HIP(hipStreamSynchronize(st));
                 if (hu == 0) break;
             }
@@ -904,7 +954,7 @@ void amg_setup(dp_sim* s) {
             int* erow = Sc.get<int>(A.nnz, "entry rows");
             int64_t* ecnt = Sc.get<int64_t>(A.nnz + 1, "interp entry count");
             int64_t* etmp = Sc.get<int64_t>(scan_tmp_size(A.nnz + 1), "scan tmp");
-            entry_rows<<<ceil_div(n, 256), 256, 0, st>>>(A, erow);
+            entry_rows<<<rl_grid(n), 256, 0, st>>>(A, erow);
             interp_beta<<<ceil_div(n, 256), 256, 0, st>>>(A, smask, L.cf, diag, beta, g);
             interp_d<<<ceil_div(n, 256), 256, 0, st>>>(A, smask, L.cf, diag, beta, dd);
             interp_count_e<<<ceil_div(A.nnz, 256), 256, 0, st>>>(A, erow, smask, L.cf, beta, g, ecnt);
@@ -1002,7 +1052,7 @@ void amg_setup(dp_sim* s) {
             int* erow = Sc.get<int>(A.nnz, "entry rows");
             int64_t* cnt = Sc.get<int64_t>(A.nnz + 1, "rap count");
             int64_t* stmp = Sc.get<int64_t>(scan_tmp_size(A.nnz + 1), "scan tmp");
-            entry_rows<<<ceil_div(n, 256), 256, 0, st>>>(A, erow);
+            entry_rows<<<rl_grid(n), 256, 0, st>>>(A, erow);
             rap_count_e<<<ceil_div(A.nnz, 256), 256, 0, st>>>(A, erow, L.P, cnt);
             DP_LAUNCH_CHECK();
             int64_t m = 0;

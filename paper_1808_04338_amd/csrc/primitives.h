@@ -10,6 +10,9 @@ int64_t scan_tmp_size(int64_t n);
 // In-place exclusive scan; returns the total (synchronises the stream).
 int64_t exclusive_scan(hipStream_t st, int64_t* data, int64_t n, int64_t* tmp, int64_t* host_total);
 
+// In-place exclusive scan without a host synchronisation (tmp: scan_tmp_size(n)).
+void scan_inplace(hipStream_t st, int64_t* data, int64_t n, int64_t* tmp);
+
 int64_t sort_tmp_size(int64_t n);
 // Sort by the low 'bits' bits; returns 0 if the result is in (k0,v0), 1 if in (k1,v1).
 int radix_sort(hipStream_t st, uint64_t* k0, double* v0, uint64_t* k1, double* v1, int64_t n,

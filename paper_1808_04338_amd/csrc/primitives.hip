@@ -85,6 +85,10 @@ static void scan_rec(hipStream_t st, int64_t* data, int64_t n, int64_t* tmp) {
     }
 }
 
+void scan_inplace(hipStream_t st, int64_t* data, int64_t n, int64_t* tmp) {
+    if (n > 0) scan_rec(st, data, n, tmp);
+}
+
 int64_t exclusive_scan(hipStream_t st, int64_t* data, int64_t n, int64_t* tmp, int64_t* host_total) {
     if (n <= 0) return 0;
     // total = last prefix + last value: keep the last value before scanning

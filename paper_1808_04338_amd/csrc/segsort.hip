@@ -9,8 +9,8 @@
 //     together) are sorted at once on the key (row, col, term index) -- rows
 //     stay inside their own index ranges, so groups need no merge;
 //   * a row that does not fit its group is handled alone by the wavefront when
-//     it has at most SW_MAX terms, else listed for a 256-thread workgroup that
-//     takes up to SB_MAX terms;
+//     it has at most SW_MAX terms, else listed for 256-thread workgroups that
+//     take up to SM_MAX terms (24 KB of LDS), then up to SB_MAX (96 KB);
 //   * a longer row makes the call return false (the caller then takes the
 //     global radix-sort path).
 // Sorting is a bitonic network on 64-bit keys; sums, compaction ranks (ballot
@@ -22,6 +22,7 @@
 namespace dp {
 
 constexpr int SW_MAX = 256;
+constexpr int SM_MAX = 1024;  // 24 KB of LDS per workgroup
 constexpr int SB_MAX = 4096;  // 96 KB of LDS per workgroup
 constexpr int SEG_TARGET = 128;  // terms per wavefront group
 constexpr int SEG_GMAX = 64;     // rows per group
@@ -235,17 +236,24 @@ __global__ void __launch_bounds__(WAVE) seg_wave(Src S, int nrows, int G, int64_
     }
 }
 
-template <class Src>
-__global__ void __launch_bounds__(256) seg_block(Src S, const int* __restrict__ longlist, int64_t* cnt,
-                                                 int* overflow) {
+// Persistent workgroups over a list of long rows (count in *nlist): rows of at
+// most MAXE terms are done here, longer ones go to the next list, or raise the
+// overflow flag when there is none.
+template <int MAXE, class Src>
+__global__ void __launch_bounds__(256) seg_block(Src S, const int* __restrict__ list, const int* nlist,
+                                                 int64_t* cnt, int* next, int* nnext, int* overflow) {
     extern __shared__ char smem[];
-    SegTile<SB_MAX>& T = *reinterpret_cast<SegTile<SB_MAX>*>(smem);
-    int r = longlist[blockIdx.x];
-    if (!fits<SB_MAX>(S, r, r + 1)) {
-        if (threadIdx.x == 0) *overflow = 1;
-        return;
+    SegTile<MAXE>& T = *reinterpret_cast<SegTile<MAXE>*>(smem);
+    const int nl = *nlist;
+    for (int q = blockIdx.x; q < nl; q += gridDim.x) {
+        int r = list[q];
+        if (fits<MAXE>(S, r, r + 1)) {
+            tile_run<256, MAXE>(T, S, r, r + 1, cnt);
+        } else if (threadIdx.x == 0) {
+            if (next) next[atomicAdd(nnext, 1)] = r;
+            else *overflow = 1;
+        }
     }
-    tile_run<256, SB_MAX>(T, S, r, r + 1, cnt);
 }
 
 // CSR copy: group g's rows [r0, r1) occupy [rowptr[r0], rowptr[r1]) of the
@@ -293,31 +301,29 @@ static bool seg_run(hipStream_t st, const Src& S, const int64_t* off, int nrows,
     int64_t* cnt = sc.get<int64_t>(nrows + 1, "segment counts");
     int64_t* tmp = sc.get<int64_t>(scan_tmp_size(nrows + 1), "scan tmp");
     int* longlist = sc.get<int>(nrows, "long rows");
-    int* flags = sc.get<int>(2, "segment flags");  // [0] long rows, [1] overflow
-    DP_HIP(hipMemsetAsync(flags, 0, 2 * sizeof(int), st));
+    int* list2 = sc.get<int>(nrows, "long rows");
+    int* flags = sc.get<int>(4, "segment flags");  // [0] long rows, [1] longer rows, [2] overflow
+    DP_HIP(hipMemsetAsync(flags, 0, 4 * sizeof(int), st));
     double avg = nrows > 0 ? (double)m / nrows : 0.0;
     int G = avg > 0 ? (int)(SEG_TARGET / avg) : SEG_GMAX;
     G = std::max(1, std::min(SEG_GMAX, G));
     int ngroups = ceil_div(nrows, G);
+    int64_t total = 0;
+    int hf[4] = {0, 0, 0, 0};
     if (nrows > 0) {
         seg_wave<Src><<<ngroups, WAVE, 0, st>>>(S, nrows, G, cnt, longlist, flags);
         DP_LAUNCH_CHECK();
-    }
-    int hf[2] = {0, 0};
-    DP_HIP(hipMemcpyAsync(hf, flags, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
-    DP_HIP(hipStreamSynchronize(st));
-    if (hf[0] > 0) {
-        size_t shm = sizeof(SegTile<SB_MAX>);
-        DP_HIP(hipFuncSetAttribute((const void*)seg_block<Src>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                   (int)shm));
-        seg_block<Src><<<hf[0], 256, shm, st>>>(S, longlist, cnt, flags + 1);
+        size_t shm_m = sizeof(SegTile<SM_MAX>), shm_b = sizeof(SegTile<SB_MAX>);
+        DP_HIP(hipFuncSetAttribute((const void*)seg_block<SB_MAX, Src>,
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm_b));
+        seg_block<SM_MAX, Src><<<1024, 256, shm_m, st>>>(S, longlist, flags, cnt, list2, flags + 1, flags + 2);
+        seg_block<SB_MAX, Src><<<256, 256, shm_b, st>>>(S, list2, flags + 1, cnt, nullptr, nullptr, flags + 2);
         DP_LAUNCH_CHECK();
-        DP_HIP(hipMemcpyAsync(hf + 1, flags + 1, sizeof(int), hipMemcpyDeviceToHost, st));
-        DP_HIP(hipStreamSynchronize(st));
-        if (hf[1]) return false;
+        // the flags arrive with the scan's synchronisation
+        DP_HIP(hipMemcpyAsync(hf, flags, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
+        exclusive_scan(st, cnt, nrows, tmp, &total);
+        if (hf[2]) return false;
     }
-    int64_t total = 0;
-    if (nrows > 0) exclusive_scan(st, cnt, nrows, tmp, &total);
     csr.n = nrows;
     csr.ncols = ncols;
     csr.nnz = total;
