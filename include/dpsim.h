@@ -244,9 +244,23 @@ dp_status dp_selftest_dense_inverse(const double *a, int32_t n, double *ainv, vo
  * algorithmic bytes one launch must move (values and indices read once, vectors
  * read and written once).  kernel 0: FP64 block SpMV of the decoupled matrix;
  * 1: block ILU(0) solve (preconditioner precision); 2: AMG V-cycle; 3:
- * residual/Jacobian assembly; 4: whole CPR-FPF apply.  After cpr_fpf_setup. */
+ * residual/Jacobian assembly; 4: whole CPR-FPF apply; 5: plain copy of one
+ * vector of 2 nb doubles (the reference for HBM traffic counters).  After
+ * cpr_fpf_setup. */
 dp_status sim_bench_kernel(dp_sim *sim, int32_t kernel, int32_t reps, double *avg_ms,
                            double *bytes);
+
+/* Live kernel timing inside the normal calls.  While a timer is on, every
+ * launch of its kernel records a pair of HIP events on the handle's stream (up
+ * to 1024 launches) and adds the launch's algorithmic bytes.  kernel: 0 FP64
+ * block SpMV of the decoupled matrix in GMRES; 1 block ILU(0) solve (its four
+ * kernels as one launch); 2 row-wise AMG products A P and R (A P) (wavefront
+ * tiles and the two workgroup tiers as one launch).  on != 0 resets and
+ * starts, 0 stops.  sim_kernel_time synchronises the stream and returns the
+ * summed device time (ms), the number of timed launches and the summed bytes. */
+dp_status sim_kernel_timer(dp_sim *sim, int32_t kernel, int32_t on);
+dp_status sim_kernel_time(dp_sim *sim, int32_t kernel, double *ms_total, int64_t *launches,
+                          double *bytes);
 
 /* Average device time (ms) of the named phase over the calls since the last
  * reset: 0 assembly, 1 setup, 2 solve, 3 SpMV, 4 preconditioner apply.

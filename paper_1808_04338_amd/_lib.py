@@ -87,6 +87,8 @@ _SIGS = {
     "sim_export_ilu": [C.c_void_p, _iptr, _iptr, _iptr, _dptr],
     "sim_amg_info": [C.c_void_p, _iptr, _iptr, _lptr],
     "sim_amg_stats": [C.c_void_p, _lptr],
+    "sim_kernel_timer": [C.c_void_p, C.c_int32, C.c_int32],
+    "sim_kernel_time": [C.c_void_p, C.c_int32, _dptr, _lptr, _dptr],
     "sim_export_amg_level": [C.c_void_p, C.c_int32, _iptr, _iptr, _iptr, _dptr, _iptr, _iptr, _dptr,
                              _lptr],
     "sim_apply_precond": [C.c_void_p, _dptr, _dptr],

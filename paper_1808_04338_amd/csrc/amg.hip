@@ -1044,7 +1044,8 @@ void amg_setup(dp_sim* s) {
         bool rap_done = false;
         {
             Csr AP;
-            if (seg_product(st, A, L.P, Sc, Sc, AP, "A P")) rap_done = seg_product(st, R, AP, Sc, H, Ac, "coarse A");
+            if (seg_product(st, A, L.P, Sc, Sc, AP, "A P", &s->kt[2]))
+                rap_done = seg_product(st, R, AP, Sc, H, Ac, "coarse A", &s->kt[2]);
             Sc.top = smark;
         }
         if (!rap_done) {

@@ -24,6 +24,10 @@ void launch_newton_update(dp_sim* s);
 // linalg.hip
 void launch_decouple(dp_sim* s);
 template <class T> void bspmv(dp_sim* s, const V2<T>* x, V2<T>* y);
+// Algorithmic bytes of one launch of a timed kernel (0 FP64 block SpMV, 1 block
+// ILU(0) solve in the preconditioner precision, 2 AMG V-cycle, 3 assembly).
+double kernel_bytes(dp_sim* s, int kernel);
+void copy_f64(dp_sim* s, const double* x, double* y, int64_t len);
 template <class T> void bresidual(dp_sim* s, const V2<T>* b, const V2<T>* x, V2<T>* y);
 template <class T> void bresidual_p(dp_sim* s, const V2<T>* b, const V2<T>* x, T* yp);
 template <class T>

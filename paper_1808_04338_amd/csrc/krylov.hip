@@ -223,6 +223,17 @@ __global__ void add3_kernel(const T* __restrict__ a, const T* __restrict__ b, T*
     if (i < len) y[i] = a[i] + b[i];
 }
 
+// plain streaming copy (the reference kernel for the HBM traffic counters)
+__global__ void copy_f64_kernel(const double2* __restrict__ x, double2* __restrict__ y, int64_t half) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < half) y[i] = x[i];
+}
+void copy_f64(dp_sim* s, const double* x, double* y, int64_t len) {
+    if (len & 1) fail(DP_E_INVALID, "copy length must be even");
+    copy_f64_kernel<<<ceil_div(len / 2, 256), 256, 0, s->stream>>>((const double2*)x, (double2*)y, len / 2);
+    DP_LAUNCH_CHECK();
+}
+
 void vec_copy(dp_sim* s, const double* x, double* y, int64_t len) {
     DP_HIP(hipMemcpyAsync(y, x, sizeof(double) * len, hipMemcpyDeviceToDevice, s->stream));
 }

@@ -41,7 +41,9 @@ bool seg_sort_reduce(hipStream_t st, const int64_t* off, int nrows, int ncols, i
 // comes from 'out', temporaries from 'sc'.  Returns false, with nothing
 // allocated from 'out', when a row of C has more terms than one workgroup
 // sorts in LDS; the caller then takes the global sort path.
-bool seg_product(hipStream_t st, const Csr& X, const Csr& Y, Arena& sc, Arena& out, Csr& C, const char* what);
+// kt (may be null): live timer of the product's tile kernels.
+bool seg_product(hipStream_t st, const Csr& X, const Csr& Y, Arena& sc, Arena& out, Csr& C, const char* what,
+                 KernelTimer* kt = nullptr);
 
 inline int bits_for(int64_t n) {
     int b = 1;

@@ -296,7 +296,8 @@ __global__ void prod_count(Csr X, Csr Y, int64_t* cnt) {
 // compacted rows (found at off[r] of rcol/rval) into the CSR from 'out'.
 template <class Src>
 static bool seg_run(hipStream_t st, const Src& S, const int64_t* off, int nrows, int ncols, int64_t m,
-                    const int* rcol, const double* rval, Arena& sc, Arena& out, Csr& csr, const char* what) {
+                    const int* rcol, const double* rval, Arena& sc, Arena& out, Csr& csr, const char* what,
+                    KernelTimer* kt = nullptr, double xbytes = 0.0) {
     if (ncols >= (1 << 28) || nrows >= (1 << 24)) return false;  // key packing
     int64_t* cnt = sc.get<int64_t>(nrows + 1, "segment counts");
     int64_t* tmp = sc.get<int64_t>(scan_tmp_size(nrows + 1), "scan tmp");
@@ -311,18 +312,26 @@ static bool seg_run(hipStream_t st, const Src& S, const int64_t* off, int nrows,
     int64_t total = 0;
     int hf[4] = {0, 0, 0, 0};
     if (nrows > 0) {
-        seg_wave<Src><<<ngroups, WAVE, 0, st>>>(S, nrows, G, cnt, longlist, flags);
-        DP_LAUNCH_CHECK();
         size_t shm_m = sizeof(SegTile<SM_MAX>), shm_b = sizeof(SegTile<SB_MAX>);
         DP_HIP(hipFuncSetAttribute((const void*)seg_block<SB_MAX, Src>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm_b));
-        seg_block<SM_MAX, Src><<<1024, 256, shm_m, st>>>(S, longlist, flags, cnt, list2, flags + 1, flags + 2);
-        seg_block<SB_MAX, Src><<<256, 256, shm_b, st>>>(S, list2, flags + 1, cnt, nullptr, nullptr, flags + 2);
-        DP_LAUNCH_CHECK();
+        int kidx;
+        {
+            // timed as one group: wavefront tiles, then the two workgroup tiers
+            KtScope ks(kt, st);
+            kidx = ks.idx;
+            seg_wave<Src><<<ngroups, WAVE, 0, st>>>(S, nrows, G, cnt, longlist, flags);
+            seg_block<SM_MAX, Src><<<1024, 256, shm_m, st>>>(S, longlist, flags, cnt, list2, flags + 1, flags + 2);
+            seg_block<SB_MAX, Src><<<256, 256, shm_b, st>>>(S, list2, flags + 1, cnt, nullptr, nullptr, flags + 2);
+            DP_LAUNCH_CHECK();
+        }
         // the flags arrive with the scan's synchronisation
         DP_HIP(hipMemcpyAsync(hf, flags, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
         exclusive_scan(st, cnt, nrows, tmp, &total);
         if (hf[2]) return false;
+        // algorithmic bytes: the sources (xbytes), term offsets and row lengths,
+        // the results (column and value)
+        if (kt && kidx >= 0) kt->bytes += xbytes + 16.0 * (nrows + 1) + 12.0 * total;
     }
     csr.n = nrows;
     csr.ncols = ncols;
@@ -348,7 +357,8 @@ bool seg_sort_reduce(hipStream_t st, const int64_t* off, int nrows, int ncols, i
     return ok;
 }
 
-bool seg_product(hipStream_t st, const Csr& X, const Csr& Y, Arena& sc, Arena& out, Csr& C, const char* what) {
+bool seg_product(hipStream_t st, const Csr& X, const Csr& Y, Arena& sc, Arena& out, Csr& C, const char* what,
+                 KernelTimer* kt) {
     size_t mark = sc.top;
     int nrows = X.n;
     int64_t* off = sc.get<int64_t>(nrows + 1, "product rows");
@@ -364,7 +374,10 @@ bool seg_product(hipStream_t st, const Csr& X, const Csr& Y, Arena& sc, Arena& o
     int* ocol = sc.get<int>(m, "product terms");
     double* oval = sc.get<double>(m, "product terms");
     ProdSrc S{off, X, Y, ocol, oval};
-    bool ok = seg_run(st, S, off, nrows, Y.ncols, m, ocol, oval, sc, out, C, what);
+    // X read once (row offsets, columns, values), Y's row offsets once per X
+    // entry and one Y entry (column, value) per term
+    double xbytes = 4.0 * (nrows + 1) + 12.0 * X.nnz + 8.0 * X.nnz + 12.0 * m;
+    bool ok = seg_run(st, S, off, nrows, Y.ncols, m, ocol, oval, sc, out, C, what, kt, xbytes);
     if (!ok || &out != &sc) sc.top = mark;
     return ok;
 }

@@ -109,6 +109,41 @@ struct PhaseTimer {
     int64_t count = 0;
 };
 
+// Live timing of one kernel (or kernel group) inside the normal calls: while
+// enabled, every launch is bracketed by a pair of HIP events on the handle's
+// stream (up to KT_CAP launches; the events are read when the timer is queried)
+// and its algorithmic bytes are added up.
+constexpr int KT_CAP = 1024;
+constexpr int KT_N = 3;  // 0 FP64 block SpMV, 1 block ILU(0) solve, 2 row-wise AMG products
+struct KernelTimer {
+    bool on = false;
+    int used = 0;
+    int64_t dropped = 0;
+    double bytes = 0;
+    std::vector<hipEvent_t> ev;  // 2 * KT_CAP
+};
+
+struct KtScope {
+    KernelTimer* t;
+    hipStream_t st;
+    int idx = -1;
+    KtScope(KernelTimer* t_, hipStream_t st_) : t(t_), st(st_) {
+        if (!t || !t->on) return;
+        if (t->used >= KT_CAP) {
+            ++t->dropped;
+            return;
+        }
+        idx = t->used++;
+        DP_HIP(hipEventRecord(t->ev[2 * idx], st));
+    }
+    void bytes(double b) {
+        if (idx >= 0) t->bytes += b;
+    }
+    ~KtScope() {
+        if (idx >= 0) (void)hipEventRecord(t->ev[2 * idx + 1], st);
+    }
+};
+
 }  // namespace dp
 
 struct dp_sim {
@@ -175,4 +210,5 @@ struct dp_sim {
     dp::PhaseTimer phase[5];
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipEvent_t pev[5][2] = {};  // per-phase start/stop (phases nest)
+    dp::KernelTimer kt[dp::KT_N];
 };

@@ -408,7 +408,9 @@ static int gmres(dp_sim* s, double rtol, int maxit, int* iters, double* rel_res)
             }
             {
                 PhaseScope ps(s, 3);
+                KtScope ks(&s->kt[0], s->stream);
                 bspmv<double>(s, (const d2*)zj, (d2*)r);
+                ks.bytes(kernel_bytes(s, 0));
             }
             dot_multi(s, s->V, len, j + 1, r, len, hb);
             cgs_update_dot(s, s->V, len, j + 1, hb, r, len, hb + 32);
@@ -646,6 +648,48 @@ static int do_timestep(dp_sim* s, double dt, dp_step_info* info) {
     return DP_OK;
 }
 
+double kernel_bytes(dp_sim* s, int kernel) {
+    const Topo& t = s->topo;
+    double n = t.n, nb = t.nb, np = t.nperf;
+    double es = s->fp32 ? 4.0 : 8.0;
+    double blocks = nb + 7 * n + n + 2 * np;     // stored blocks of the matrix
+    double idx = 4.0 * (6 * n + 3 * n + 3 * np) + n;  // fcol, fcell, frow, fperf, perforations, fmask
+    double vec = 16.0 * nb;
+    if (kernel == 0) return blocks * 32.0 + idx + 2 * vec;
+    if (kernel == 1) {
+        // factors: U^-1 diagonals, L blocks (odd rows 7, even rows 1), U blocks taken
+        // from the matrix (even rows 6, matrix rows 1), perforation blocks
+        double fblocks = nb + 4 * n + 3 * n + n + 2 * np;
+        return fblocks * 4 * es + idx + 2 * nb * 2 * es;
+    }
+    if (kernel == 2) {
+        double b = 0;
+        for (size_t l = 0; l < s->levels.size(); ++l) {
+            const AmgLevel& L = s->levels[l];
+            if (l + 1 == s->levels.size()) {
+                b += (double)L.n * L.n * es + 2.0 * L.n * es;
+                break;
+            }
+            // two sweeps over A (pre: b, dinv gathered; post: x), P and R once,
+            // vectors: b, x, r, t, dinv
+            auto opb = [&](const Op& o) {
+                return o.kind == 0 ? o.s.nel * (4 + es) + 4.0 * (o.s.nslices + 1)
+                                   : o.nnz * (4 + es) + 4.0 * (o.n + 1);
+            };
+            b += 2.0 * opb(L.Aop) + opb(L.Pop) + opb(L.Rop);
+            b += 8.0 * L.n * es;
+        }
+        return b;
+    }
+    if (kernel == 3) {
+        // state, old accumulation, geometry read; residual and J written
+        return 16.0 * nb + 16.0 * 2 * n + 8.0 * (6 * n + 4 * n + np) + idx + 16.0 * nb +
+               blocks * 32.0;
+    }
+    if (kernel == 5) return 2.0 * 16.0 * nb;  // plain copy of the 2 nb doubles: read + write
+    return 0.0;
+}
+
 }  // namespace dp
 
 // ===========================================================================
@@ -826,6 +870,9 @@ dp_status sim_destroy(dp_sim* sim) {
     if (sim->ev1) (void)hipEventDestroy(sim->ev1);
     for (auto& pe : sim->pev)
         for (auto& e : pe)
+            if (e) (void)hipEventDestroy(e);
+    for (auto& t : sim->kt)
+        for (auto& e : t.ev)
             if (e) (void)hipEventDestroy(e);
     delete sim;
     return DP_OK;
@@ -1250,49 +1297,9 @@ dp_status sim_apply_stage(dp_sim* sim, int32_t stage, const double* r, double* z
     ABI_END(sim)
 }
 
-static double bench_bytes(dp_sim* s, int kernel) {
-    const Topo& t = s->topo;
-    double n = t.n, nb = t.nb, np = t.nperf;
-    double es = s->fp32 ? 4.0 : 8.0;
-    double blocks = nb + 7 * n + n + 2 * np;     // stored blocks of the matrix
-    double idx = 4.0 * (6 * n + 3 * n + 3 * np) + n;  // fcol, fcell, frow, fperf, perforations, fmask
-    double vec = 16.0 * nb;
-    if (kernel == 0) return blocks * 32.0 + idx + 2 * vec;
-    if (kernel == 1) {
-        // factors: U^-1 diagonals, L blocks (odd rows 7, even rows 1), U blocks taken
-        // from the matrix (even rows 6, matrix rows 1), perforation blocks
-        double fblocks = nb + 4 * n + 3 * n + n + 2 * np;
-        return fblocks * 4 * es + idx + 2 * nb * 2 * es;
-    }
-    if (kernel == 2) {
-        double b = 0;
-        for (size_t l = 0; l < s->levels.size(); ++l) {
-            const AmgLevel& L = s->levels[l];
-            if (l + 1 == s->levels.size()) {
-                b += (double)L.n * L.n * es + 2.0 * L.n * es;
-                break;
-            }
-            // two sweeps over A (pre: b, dinv gathered; post: x), P and R once,
-            // vectors: b, x, r, t, dinv
-            auto opb = [&](const Op& o) {
-                return o.kind == 0 ? o.s.nel * (4 + es) + 4.0 * (o.s.nslices + 1)
-                                   : o.nnz * (4 + es) + 4.0 * (o.n + 1);
-            };
-            b += 2.0 * opb(L.Aop) + opb(L.Pop) + opb(L.Rop);
-            b += 8.0 * L.n * es;
-        }
-        return b;
-    }
-    if (kernel == 3) {
-        // state, old accumulation, geometry read; residual and J written
-        return 16.0 * nb + 16.0 * 2 * n + 8.0 * (6 * n + 4 * n + np) + idx + 16.0 * nb +
-               blocks * 32.0;
-    }
-    return 0.0;
-}
 
 dp_status sim_bench_kernel(dp_sim* sim, int32_t kernel, int32_t reps, double* avg_ms, double* bytes) {
-    if (!sim || kernel < 0 || kernel > 4 || reps <= 0) return DP_E_INVALID;
+    if (!sim || kernel < 0 || kernel > 5 || reps <= 0) return DP_E_INVALID;
     ABI_BEGIN
     if (sim->stage < 2) fail(DP_E_STATE, "kernel timing needs cpr_fpf_setup first");
     int64_t len = 2 * (int64_t)sim->topo.nb;
@@ -1312,6 +1319,9 @@ dp_status sim_bench_kernel(dp_sim* sim, int32_t kernel, int32_t reps, double* av
             case 3:
                 launch_assemble(sim, sim->dt_assembled);
                 break;
+            case 5:
+                copy_f64(sim, (const double*)sim->rhs, sim->w, len);
+                break;
             default:
                 cpr_apply(sim, (const double*)sim->rhs, sim->w);
         }
@@ -1325,7 +1335,44 @@ dp_status sim_bench_kernel(dp_sim* sim, int32_t kernel, int32_t reps, double* av
     float ms = 0.f;
     DP_HIP(hipEventElapsedTime(&ms, sim->ev0, sim->ev1));
     if (avg_ms) *avg_ms = ms / reps;
-    if (bytes) *bytes = bench_bytes(sim, kernel);
+    if (bytes) *bytes = kernel_bytes(sim, kernel);
+    return DP_OK;
+    ABI_END(sim)
+}
+
+dp_status sim_kernel_timer(dp_sim* sim, int32_t kernel, int32_t on) {
+    if (!sim || kernel < 0 || kernel >= KT_N) return DP_E_INVALID;
+    ABI_BEGIN
+    KernelTimer& t = sim->kt[kernel];
+    if (on && t.ev.empty()) {
+        t.ev.assign(2 * KT_CAP, nullptr);
+        for (auto& e : t.ev) DP_HIP(hipEventCreate(&e));
+    }
+    DP_HIP(hipStreamSynchronize(sim->stream));
+    t.on = on != 0;
+    if (on) {
+        t.used = 0;
+        t.dropped = 0;
+        t.bytes = 0;
+    }
+    return DP_OK;
+    ABI_END(sim)
+}
+
+dp_status sim_kernel_time(dp_sim* sim, int32_t kernel, double* ms_total, int64_t* launches, double* bytes) {
+    if (!sim || kernel < 0 || kernel >= KT_N) return DP_E_INVALID;
+    ABI_BEGIN
+    KernelTimer& t = sim->kt[kernel];
+    DP_HIP(hipStreamSynchronize(sim->stream));
+    double tot = 0.0;
+    for (int i = 0; i < t.used; ++i) {
+        float ms = 0.f;
+        DP_HIP(hipEventElapsedTime(&ms, t.ev[2 * i], t.ev[2 * i + 1]));
+        tot += ms;
+    }
+    if (ms_total) *ms_total = tot;
+    if (launches) *launches = t.used;
+    if (bytes) *bytes = t.bytes;
     return DP_OK;
     ABI_END(sim)
 }

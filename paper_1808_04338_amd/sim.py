@@ -207,6 +207,20 @@ class Sim:
         self._chk(self.lib.sim_amg_info(self.h, C.byref(nl), _ip(rows), _lp(nnz)))
         return nl.value, rows[:nl.value].copy(), nnz[:nl.value].copy()
 
+    TIMED_KERNELS = ("block_spmv_f64", "block_ilu0_solve", "amg_rowwise_products")
+
+    def kernel_timer(self, kernel, on=True):
+        """Start (reset) or stop the live timer of kernel 0, 1 or 2 (TIMED_KERNELS)."""
+        self._chk(self.lib.sim_kernel_timer(self.h, int(kernel), 1 if on else 0))
+
+    def kernel_time(self, kernel):
+        """(total device ms, timed launches, algorithmic bytes) since the timer started."""
+        ms = C.c_double()
+        n = C.c_int64()
+        b = C.c_double()
+        self._chk(self.lib.sim_kernel_time(self.h, int(kernel), C.byref(ms), C.byref(n), C.byref(b)))
+        return ms.value, n.value, b.value
+
     def amg_global_sort_products(self):
         """AMG products (one per level and setup) formed by the global sort path."""
         v = C.c_int64()
@@ -257,7 +271,8 @@ class Sim:
         self._chk(self.lib.sim_apply_matrix(self.h, _dp(x), _dp(y)))
         return y
 
-    KERNELS = ["block_spmv_f64", "block_ilu0_solve", "amg_vcycle", "assemble", "cpr_fpf_apply"]
+    KERNELS = ["block_spmv_f64", "block_ilu0_solve", "amg_vcycle", "assemble", "cpr_fpf_apply",
+               "copy_f64"]
 
     def bench_kernel(self, kernel, reps=20):
         """(average ms per launch, algorithmic bytes per launch) of a kernel group."""
