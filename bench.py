@@ -188,6 +188,10 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--amg-coarse-max", type=int, default=0,
                     help="largest coarsest AMG level (0: the library default)")
+    ap.add_argument("--amg-theta", type=float, default=0.0,
+                    help="AMG strength threshold (0: the library default)")
+    ap.add_argument("--amg-trunc", type=int, default=0,
+                    help="interpolation entries kept per row (0: the library default)")
     ap.add_argument("--no-kernels", action="store_true",
                     help="skip the per-kernel timings (kernels list and roofline)")
     ap.add_argument("--served", type=int, default=16,
@@ -206,6 +210,10 @@ def main():
     opts = {}
     if args.amg_coarse_max:
         opts["amg_coarse_max"] = args.amg_coarse_max
+    if args.amg_theta:
+        opts["amg_theta"] = args.amg_theta
+    if args.amg_trunc:
+        opts["amg_trunc"] = args.amg_trunc
     r32, state = timed_form(model, "fp32", args.steps, args.warmup, args.rtol,
                             kernels=not args.no_kernels, **opts)
     r64 = None

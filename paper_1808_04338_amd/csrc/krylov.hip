@@ -112,12 +112,28 @@ __global__ void __launch_bounds__(RBLK) red_kernel(const double* __restrict__ V,
     __syncthreads();
     if (!last) return;
     __threadfence();
-    // last block: wave wv sums result k = wv, wv + 4, ... over the blocks
-    for (int k = wv; k < nres; k += RBLK / WAVE) {
+    // last block: thread t adds the partials of blocks t, t + RBLK, ... for every
+    // result (independent loads), then one block reduction per result
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += RBLK) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k)
+            if (k < nres) acc[k] += part[(int64_t)b * KMAX + k];
+    }
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        if (k < nres) {
+            double v = wave_sum(acc[k]);
+            if (lane == 0) sh[k][wv] = v;
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nres) {
         double v = 0.0;
-        for (int b = lane; b < (int)gridDim.x; b += WAVE) v += part[(int64_t)b * KMAX + k];
-        v = wave_sum(v);
-        if (lane == 0) out[k] = v;
+#pragma unroll
+        for (int q = 0; q < RBLK / WAVE; ++q) v += sh[threadIdx.x][q];
+        out[threadIdx.x] = v;
     }
     if (threadIdx.x == 0) *count = 0u;
 }
