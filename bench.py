@@ -176,6 +176,36 @@ def served_leg(count):
     return summ
 
 
+def forcing_study(steps):
+    """Fixed eta (lin_rtol 1e-6) against the three adaptive forcing terms of
+    Eq. (13): the first `steps` 5-day steps of the 144k-DOF layered model, FP32
+    preconditioner.  Returns one record per choice."""
+    import torch
+
+    import synth
+    from paper_1808_04338_amd import Sim
+
+    model = synth.model_layered()
+    out = []
+    for choice in (0, 1, 2, 3):
+        sim = Sim(model, precision="fp32", forcing=choice)
+        newton = lin = cuts = 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            info = sim.timestep(model["schedule"][k])
+            newton += info["newton_iters"]
+            lin += info["lin_iters"]
+            cuts += info["cuts"]
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        sim.close()
+        out.append(dict(forcing=choice, timesteps=steps, newton_iters=newton, lin_iters=lin, cuts=cuts,
+                        lin_per_newton=lin / max(newton, 1), wall_s=wall))
+        log("forcing %d: %d Newton, %d GMRES iterations, %.2f s" % (choice, newton, lin, wall))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -196,6 +226,9 @@ def main():
                     help="skip the per-kernel timings (kernels list and roofline)")
     ap.add_argument("--served", type=int, default=16,
                     help="requests of the served-ensemble leg (0 to skip)")
+    ap.add_argument("--forcing-study", type=int, default=0,
+                    help="instead of the benchmark: that many timesteps of the 144k-DOF model with "
+                         "each forcing choice of Eq. (13)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -204,6 +237,13 @@ def main():
     import torch
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.forcing_study > 0:
+        rec = forcing_study(args.forcing_study)
+        print(json.dumps({"study": "inexact-Newton forcing terms (Eq. (13)) vs fixed eta = 1e-6",
+                          "workload": "dual-porosity oil-water 60x60x10 layered five-spot, 144,010 DOF, "
+                                      "5-day steps, FP32 preconditioner",
+                          "data": "synthetic", "results": rec}))
+        return
     log("generating the 60x220x%d model" % args.nz)
     model = make_model(args.nz)
     log("FP32-preconditioner form")

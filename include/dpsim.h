@@ -105,6 +105,20 @@ typedef struct {
     int32_t max_cuts;         /* [8] */
     double mb_tol;            /* MB: per phase |sum_nodes R| dt / sum_nodes(rho_ref phi V) [1e-7];
                                  Newton has converged when CNV <= newton_tol and MB <= mb_tol */
+    /* Linear tolerance eta_l of timestep's Newton iterations (Algorithm 1, Eq. (12)):
+     * forcing 0 keeps lin_rtol; 1, 2, 3 select the adaptive choices of Eq. (13):
+     * eta_l = ||b_l - r_{l-1}|| / ||b_{l-1}||, | ||b_l|| - ||r_{l-1}|| | / ||b_{l-1}||, or
+     * gamma (||b_l|| / ||b_{l-1}||)^beta, with b = -R and r_{l-1} = b_{l-1} - J_{l-1} y_{l-1}
+     * (2-norms of the undecoupled system); the first iteration uses forcing_eta0;
+     * safeguards: choices 1-2 max(eta, eta_{l-1}^phi) if eta_{l-1}^phi > 0.1 (phi the
+     * golden ratio), choice 3 max(eta, gamma eta_{l-1}^beta) if that exceeds 0.1; then
+     * eta is clamped to [forcing_eta_min, forcing_eta_max]. */
+    int32_t forcing;          /* [0] */
+    double forcing_eta0;      /* [0.1] */
+    double forcing_gamma;     /* [0.9] */
+    double forcing_beta;      /* [2], in (1, 2] */
+    double forcing_eta_min;   /* [1e-8] */
+    double forcing_eta_max;   /* [0.9] */
 } dp_sim_desc;
 
 typedef struct {
@@ -206,6 +220,11 @@ dp_status sim_export_ilu(dp_sim *sim, int32_t *perm, int32_t *brow, int32_t *bco
 
 /* AMG hierarchy sizes: levels, rows[l], nnz[l] (arrays of amg_max_levels). */
 dp_status sim_amg_info(dp_sim *sim, int32_t *levels, int32_t *rows, int64_t *nnz);
+
+/* Linear tolerances eta_l used by the Newton iterations of the last timestep
+ * call, in order, across its sub-steps (lin_rtol each when forcing = 0).  Copies
+ * at most cap values into eta (host) and stores the full count. */
+dp_status sim_eta_history(dp_sim *sim, double *eta, int32_t cap, int32_t *count);
 
 /* Setup statistics since sim_create: the number of AMG products (interpolation
  * or Galerkin, one per level and setup) that had a row too long for the

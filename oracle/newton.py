@@ -3,9 +3,11 @@ timestep loop and the material-balance report.
 
 Part of the CPU oracle (test infrastructure only; see the package docstring).
 
-Algorithm 1 (inexact Newton) with the forcing term fixed: the linear system
-J y = -R is solved by SuperLU (``linear='lu'``) or by the oracle's own
-decoupled CPR-FPF GMRES (``linear='cpr'``, relative tolerance ``eta``).
+Algorithm 1 (inexact Newton): the linear system J y = -R is solved by SuperLU
+(``linear='lu'``) or by the oracle's own decoupled CPR-FPF GMRES
+(``linear='cpr'``) to the relative tolerance eta_l of Eq. (12).  eta_l is fixed
+(``forcing=0``, eta_l = ``eta``) or one of the three adaptive choices of
+Eq. (13) (``forcing=1, 2, 3``, see ``forcing_term``).
 
 Readings (the paper does not state them): the update chops the saturation
 change of each node to at most 0.2 per iteration, stops it at the
@@ -81,13 +83,48 @@ def apply_update(geo, x, dx, control):
     return y
 
 
+GOLDEN = (1.0 + 5.0 ** 0.5) / 2.0
+
+
+def forcing_term(choice, eta_prev, nb, nb_prev, nr_prev, nd, gamma=0.9, beta=2.0, eta_max=0.9,
+                 eta_min=1e-8):
+    """Adaptive forcing term eta_l of Eq. (13) for l >= 1.
+
+    nb = ||b(x^l)||, nb_prev = ||b(x^{l-1})||, nr_prev = ||r^{l-1}|| with
+    r^{l-1} = b(x^{l-1}) - J(x^{l-1}) y^{l-1} the linear residual of the previous
+    iteration, nd = ||b(x^l) - r^{l-1}|| (2-norms of the undecoupled Newton
+    right-hand side b = -R).  Choice 1: nd / nb_prev; choice 2: |nb - nr_prev| /
+    nb_prev (the absolute value the printed formula lacks, by reading); choice
+    3: gamma (nb / nb_prev)^beta.  Safeguards (by reading, Eisenstat and
+    Walker's): choices 1-2 take max(eta, eta_prev^phi) when eta_prev^phi > 0.1,
+    phi the golden ratio; choice 3 takes max(eta, gamma eta_prev^beta) when that
+    exceeds 0.1; finally eta is clamped to [eta_min, eta_max]."""
+    if choice == 1:
+        eta = nd / nb_prev
+        guard = eta_prev ** GOLDEN
+    elif choice == 2:
+        eta = abs(nb - nr_prev) / nb_prev
+        guard = eta_prev ** GOLDEN
+    elif choice == 3:
+        eta = gamma * (nb / nb_prev) ** beta
+        guard = gamma * eta_prev ** beta
+    else:
+        raise ValueError("forcing choice must be 1, 2 or 3")
+    if guard > 0.1:
+        eta = max(eta, guard)
+    return min(max(eta, eta_min), eta_max)
+
+
 def newton_solve(geo, x0, acc_old, dt, control, tol=1e-10, max_newton=20,
-                 linear="lu", eta=1e-10, cpr_opts=None, mb_tol=1e-7):
+                 linear="lu", eta=1e-10, cpr_opts=None, mb_tol=1e-7, forcing=0, eta0=0.1,
+                 forcing_opts=None):
     """Newton iterations from x0.  Converged when the scaled max-norm (CNV) is at
-    most tol and the material-balance measure at most mb_tol.  Returns
-    (x, converged, iterations, info)."""
+    most tol and the material-balance measure at most mb_tol.  With forcing 1-3
+    the first linear tolerance is eta0 and the later ones follow Eq. (13).
+    Returns (x, converged, iterations, info); info["eta"] lists the tolerances."""
     x = x0.copy()
-    info = {"res": [], "lin_iters": []}
+    info = {"res": [], "lin_iters": [], "eta": []}
+    prev = None  # (eta, ||b||, ||r||, r) of the previous iteration
     for it in range(max_newton + 1):
         R = ph.residual(geo, x, acc_old, dt, control)
         nrm = scaled_residual_norm(geo, R, dt, control)
@@ -99,6 +136,16 @@ def newton_solve(geo, x0, acc_old, dt, control, tol=1e-10, max_newton=20,
         if it == max_newton:
             break
         J = ph.jacobian(geo, x, dt, control)
+        b = -R
+        if forcing:
+            nb = float(np.linalg.norm(b))
+            if prev is None:
+                eta = eta0
+            else:
+                e_prev, nb_prev, nr_prev, r_prev = prev
+                nd = float(np.linalg.norm(b - r_prev))
+                eta = forcing_term(forcing, e_prev, nb, nb_prev, nr_prev, nd, **(forcing_opts or {}))
+        info["eta"].append(eta)
         # a singular or numerically failed linear stage counts as a failed iteration
         try:
             if linear == "lu":
@@ -114,6 +161,9 @@ def newton_solve(geo, x0, acc_old, dt, control, tol=1e-10, max_newton=20,
             return x, False, it, info
         if not np.all(np.isfinite(dx)):
             return x, False, it, info
+        if forcing:
+            r = b - J @ dx
+            prev = (eta, nb, float(np.linalg.norm(r)), r)
         x = apply_update(geo, x, dx, control)
     return x, False, max_newton, info
 
@@ -174,7 +224,7 @@ def timestep(geo, x, dt, control, max_cuts=8, **newton_kw):
         mo_old, mw_old = float(np.sum(acc_old[0])), float(np.sum(acc_old[1]))
         mo_new, mw_new = float(np.sum(acc_new[0])), float(np.sum(acc_new[1]))
         report.append(dict(dt=h, newton=its, lin_iters=info["lin_iters"],
-                           res=info["res"],
+                           res=info["res"], eta=info["eta"],
                            mb_oil=_rel(mo_new - mo_old - h * qo, mo_new),
                            mb_water=_rel(mw_new - mw_old - h * qw, mw_new),
                            control=list(control)))

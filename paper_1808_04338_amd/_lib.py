@@ -53,7 +53,10 @@ class DpSimDesc(C.Structure):
                 ("amg_coarse_max", C.c_int32), ("amg_max_levels", C.c_int32),
                 ("amg_theta", C.c_double), ("amg_trunc", C.c_int32),
                 ("newton_tol", C.c_double), ("max_newton", C.c_int32), ("max_cuts", C.c_int32),
-                ("mb_tol", C.c_double)]
+                ("mb_tol", C.c_double),
+                ("forcing", C.c_int32), ("forcing_eta0", C.c_double), ("forcing_gamma", C.c_double),
+                ("forcing_beta", C.c_double), ("forcing_eta_min", C.c_double),
+                ("forcing_eta_max", C.c_double)]
 
 
 class DpNewtonInfo(C.Structure):
@@ -87,6 +90,7 @@ _SIGS = {
     "sim_export_ilu": [C.c_void_p, _iptr, _iptr, _iptr, _dptr],
     "sim_amg_info": [C.c_void_p, _iptr, _iptr, _lptr],
     "sim_amg_stats": [C.c_void_p, _lptr],
+    "sim_eta_history": [C.c_void_p, _dptr, C.c_int32, _iptr],
     "sim_kernel_timer": [C.c_void_p, C.c_int32, C.c_int32],
     "sim_kernel_time": [C.c_void_p, C.c_int32, _dptr, _lptr, _dptr],
     "sim_export_amg_level": [C.c_void_p, C.c_int32, _iptr, _iptr, _iptr, _dptr, _iptr, _iptr, _dptr,

@@ -24,6 +24,7 @@ void launch_newton_update(dp_sim* s);
 // linalg.hip
 void launch_decouple(dp_sim* s);
 template <class T> void bspmv(dp_sim* s, const V2<T>* x, V2<T>* y);
+void jspmv(dp_sim* s, const d2* x, d2* y);  // y = J x, undecoupled Jacobian
 // Algorithmic bytes of one launch of a timed kernel (0 FP64 block SpMV, 1 block
 // ILU(0) solve in the preconditioner precision, 2 AMG V-cycle, 3 assembly).
 double kernel_bytes(dp_sim* s, int kernel);

@@ -335,6 +335,14 @@ void bresidual_prol(dp_sim* s, const V2<T>* b, const V2<T>* x, const T* e, V2<T>
     sp_launch<T, MODE_PROL>(s, a);
 }
 
+// y = J x with the undecoupled Jacobian (FP64)
+void jspmv(dp_sim* s, const d2* x, d2* y) {
+    SpArgs<double> a = sp_args<double>(s, s->J);
+    a.x = x;
+    a.y = y;
+    sp_launch<double, MODE_Y>(s, a);
+}
+
 template void bspmv<double>(dp_sim*, const d2*, d2*);
 template void bspmv<float>(dp_sim*, const f2*, f2*);
 template void bresidual<double>(dp_sim*, const d2*, const d2*, d2*);

@@ -170,6 +170,9 @@ struct dp_sim {
     dp::d2* res = nullptr;      // R
     dp::d2* rhs = nullptr;      // decoupled right-hand side -D^-1 R
     dp::d2* dx = nullptr;       // Newton correction
+    dp::d2* ft = nullptr;       // adaptive forcing: R + J dx of the previous iteration
+    dp::d2* fu = nullptr;       // adaptive forcing: work vector
+    std::vector<double> eta_hist;  // linear tolerances of the last timestep's Newton iterations
     double dt_assembled = 0.0;
     int stage = 0;              // 0 nothing, 1 assembled, 2 setup done
 

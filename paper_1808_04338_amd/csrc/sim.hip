@@ -28,6 +28,11 @@ static void fill_defaults(dp_sim_desc& d) {
     if (d.amg_trunc <= 0) d.amg_trunc = 3;
     if (d.newton_tol <= 0) d.newton_tol = 1e-3;
     if (d.mb_tol <= 0) d.mb_tol = 1e-7;
+    if (d.forcing_eta0 <= 0) d.forcing_eta0 = 0.1;
+    if (d.forcing_gamma <= 0) d.forcing_gamma = 0.9;
+    if (d.forcing_beta <= 0) d.forcing_beta = 2.0;
+    if (d.forcing_eta_min <= 0) d.forcing_eta_min = 1e-8;
+    if (d.forcing_eta_max <= 0) d.forcing_eta_max = 0.9;
     if (d.max_newton <= 0) d.max_newton = 20;
     if (d.max_cuts <= 0) d.max_cuts = 8;
 }
@@ -44,6 +49,10 @@ static void validate(const dp_sim_desc& d) {
     if (!(d.swc >= 0 && d.sor >= 0 && d.swc + d.sor < 1)) fail(DP_E_INVALID, "bad Corey end points");
     if (d.precond_precision != DP_FP64 && d.precond_precision != DP_FP32)
         fail(DP_E_INVALID, "precond_precision must be DP_FP64 or DP_FP32");
+    if (d.forcing < 0 || d.forcing > 3) fail(DP_E_INVALID, "forcing must be 0, 1, 2 or 3");
+    if (d.forcing && !(d.forcing_beta > 1.0 && d.forcing_beta <= 2.0 && d.forcing_gamma <= 1.0 &&
+                       d.forcing_eta_min <= d.forcing_eta_max && d.forcing_eta_max < 1.0))
+        fail(DP_E_INVALID, "forcing parameters out of range");
     for (int w = 0; w < d.nwells; ++w) {
         const dp_well& wl = d.wells[w];
         if (wl.i < 0 || wl.i >= d.nx || wl.j < 0 || wl.j >= d.ny || wl.k0 < 0 || wl.k1 >= d.nz ||
@@ -212,6 +221,10 @@ static Layout layout(dp_sim* s, Arena& a, const HostTopo& h) {
     s->res = a.get<d2>(nb, "residual");
     s->rhs = a.get<d2>(nb, "rhs");
     s->dx = a.get<d2>(nb, "correction");
+    if (s->desc.forcing) {
+        s->ft = a.get<d2>(nb, "forcing terms");
+        s->fu = a.get<d2>(nb, "forcing terms");
+    }
     alloc_bmat(a, s->J, n, nb, nperf, "jacobian");
     alloc_bmat(a, s->A, n, nb, nperf, "decoupled matrix");
     size_t es = s->fp32 ? 4 : 8;
@@ -553,15 +566,64 @@ static int solve(dp_sim* s, double rtol, int maxit, int* its, double* rel) {
     return gmres(s, rtol, maxit, its, rel);
 }
 
+// Adaptive forcing term eta_l of Eq. (13) for l >= 1 (the readings are stated
+// with the descriptor's forcing fields).
+static double forcing_term(const dp_sim_desc& d, double eta_prev, double nb, double nb_prev,
+                           double nr_prev, double nd) {
+    const double phi = 0.5 * (1.0 + std::sqrt(5.0));
+    double eta, guard;
+    if (d.forcing == 1) {
+        eta = nd / nb_prev;
+        guard = std::pow(eta_prev, phi);
+    } else if (d.forcing == 2) {
+        eta = std::fabs(nb - nr_prev) / nb_prev;
+        guard = std::pow(eta_prev, phi);
+    } else {
+        eta = d.forcing_gamma * std::pow(nb / nb_prev, d.forcing_beta);
+        guard = d.forcing_gamma * std::pow(eta_prev, d.forcing_beta);
+    }
+    if (guard > 0.1) eta = std::max(eta, guard);
+    return std::min(std::max(eta, d.forcing_eta_min), d.forcing_eta_max);
+}
+
+// 2-norm of a device vector of 2 nb doubles (synchronises).
+static double dev_norm(dp_sim* s, const double* x) {
+    int64_t len = 2 * (int64_t)s->topo.nb;
+    double* out = s->red_out + 128;
+    norm2(s, x, len, out);
+    double h = 0;
+    DP_HIP(hipMemcpyAsync(&h, out, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    DP_HIP(hipStreamSynchronize(s->stream));
+    return std::sqrt(h);
+}
+
 // One sub-step of length h from the current state; returns true on convergence.
 static bool newton_loop(dp_sim* s, double h, int* newton_its, int* lin_its, double* res_out) {
     const dp_sim_desc& d = s->desc;
+    int64_t len = 2 * (int64_t)s->topo.nb;
+    // previous iteration's eta, ||b||, ||r|| (b = -R; r = b - J y, stored negated in ft)
+    bool have_prev = false;
+    double eta_prev = 0, nb_prev = 0, nr_prev = 0;
     for (int it = 0; it <= d.max_newton; ++it) {
         ResNorm nrm = assemble(s, h);
         *res_out = nrm.cnv;
         if (!finite(nrm)) return false;
         if (converged(s, nrm)) return true;
         if (it == d.max_newton) break;
+        double eta = d.lin_rtol, nb = 0;
+        if (d.forcing) {
+            nb = dev_norm(s, (const double*)s->res);
+            if (!have_prev) {
+                eta = d.forcing_eta0;
+            } else {
+                // ||b_l - r_{l-1}|| = ||R_l - ft|| with ft = R_{l-1} + J_{l-1} y_{l-1}
+                double* dvec = (double*)s->fu;
+                vec_copy(s, (const double*)s->res, dvec, len);
+                vec_axpy(s, -1.0, (const double*)s->ft, dvec, len);
+                double nd = dev_norm(s, dvec);
+                eta = forcing_term(d, eta_prev, nb, nb_prev, nr_prev, nd);
+            }
+        }
         // a singular preconditioner (zero pivot) counts as a failed iteration
         try {
             setup(s);
@@ -569,11 +631,22 @@ static bool newton_loop(dp_sim* s, double h, int* newton_its, int* lin_its, doub
             if (e.code != DP_E_NUMERIC) throw;
             return false;
         }
+        s->eta_hist.push_back(eta);
         int li = 0;
         double rr = 0;
-        int st = solve(s, d.lin_rtol, d.lin_maxit, &li, &rr);
+        int st = solve(s, eta, d.lin_maxit, &li, &rr);
         *lin_its += li;
         if (st == DP_E_NUMERIC) return false;
+        if (d.forcing) {
+            // ft = R + J dx = -(b - J y): the negated linear residual of this iteration
+            jspmv(s, (const d2*)s->dx, s->fu);
+            vec_copy(s, (const double*)s->res, (double*)s->ft, len);
+            vec_axpy(s, 1.0, (const double*)s->fu, (double*)s->ft, len);
+            nr_prev = dev_norm(s, (const double*)s->ft);
+            nb_prev = nb;
+            eta_prev = eta;
+            have_prev = true;
+        }
         launch_newton_update(s);
         ++*newton_its;
     }
@@ -582,6 +655,7 @@ static bool newton_loop(dp_sim* s, double h, int* newton_its, int* lin_its, doub
 
 static int do_timestep(dp_sim* s, double dt, dp_step_info* info) {
     const dp_sim_desc& d = s->desc;
+    s->eta_hist.clear();
     dp_step_info out{};
     std::vector<int> ctrl0 = host_ctrl(s);
     std::vector<int> ctrl = ctrl0;
@@ -1191,6 +1265,14 @@ dp_status sim_amg_info(dp_sim* sim, int32_t* levels, int32_t* rows, int64_t* nnz
         if (rows) rows[l] = sim->levels[l].n;
         if (nnz) nnz[l] = sim->levels[l].A.nnz;
     }
+    return DP_OK;
+}
+
+dp_status sim_eta_history(dp_sim* sim, double* eta, int32_t cap, int32_t* count) {
+    if (!sim || cap < 0 || (cap > 0 && !eta)) return DP_E_INVALID;
+    int32_t n = (int32_t)sim->eta_hist.size();
+    for (int32_t i = 0; i < n && i < cap; ++i) eta[i] = sim->eta_hist[i];
+    if (count) *count = n;
     return DP_OK;
 }
 

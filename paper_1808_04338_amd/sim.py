@@ -71,6 +71,12 @@ def make_desc(model, precision=None, **opts):
     d.max_newton = int(opts.get("max_newton", 20))
     d.max_cuts = int(opts.get("max_cuts", 8))
     d.mb_tol = float(opts.get("mb_tol", 1e-7))
+    d.forcing = int(opts.get("forcing", 0))
+    d.forcing_eta0 = float(opts.get("forcing_eta0", 0.1))
+    d.forcing_gamma = float(opts.get("forcing_gamma", 0.9))
+    d.forcing_beta = float(opts.get("forcing_beta", 2.0))
+    d.forcing_eta_min = float(opts.get("forcing_eta_min", 1e-8))
+    d.forcing_eta_max = float(opts.get("forcing_eta_max", 0.9))
     return d, keep
 
 
@@ -220,6 +226,14 @@ class Sim:
         b = C.c_double()
         self._chk(self.lib.sim_kernel_time(self.h, int(kernel), C.byref(ms), C.byref(n), C.byref(b)))
         return ms.value, n.value, b.value
+
+    def eta_history(self):
+        """Linear tolerances of the last timestep's Newton iterations."""
+        n = C.c_int32()
+        self._chk(self.lib.sim_eta_history(self.h, None, 0, C.byref(n)))
+        out = np.zeros(max(n.value, 1))
+        self._chk(self.lib.sim_eta_history(self.h, _dp(out), n.value, C.byref(n)))
+        return out[:n.value].copy()
 
     def amg_global_sort_products(self):
         """AMG products (one per level and setup) formed by the global sort path."""

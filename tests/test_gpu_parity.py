@@ -289,3 +289,57 @@ def test_error_paths():
         sim.export_system(1)
     assert e.value.code == DP_E_STATE
     sim.close()
+
+
+@pytest.mark.parametrize("choice", [1, 2, 3])
+def test_adaptive_forcing_matches_oracle(choice):
+    """Eq. (13) forcing terms: one 5-day step of the 1,200-DOF model with a
+    multi-level (inexact) AMG on both sides.  The GPU and oracle reach the same
+    converged state and compute the same tolerance after the first iteration."""
+    from paper_1808_04338_amd import Sim
+
+    m = synth.model_small()
+    dt = 5.0 * synth.DAY
+    sim = Sim(m, precision="fp64", newton_tol=1e-10, forcing=choice, forcing_eta0=1e-4, amg_coarse_max=20,
+              max_newton=40)
+    info = sim.timestep(dt)
+    pg, sg, bg = sim.get_state()
+    sim_eta = sim.eta_history()
+    sim.close()
+    geo = oph.Geometry(m)
+    x, rep, _ = onewton.timestep(geo, oph.initial_state(m), dt, controls(m), tol=1e-10, linear="cpr",
+                                 forcing=choice, eta0=1e-4, max_newton=40,
+                                 cpr_opts=dict(amg_opts=dict(max_coarse=20)))
+    po, so, bo = oph.unpack_state(x, geo.n)
+    assert rel_max(pg, po) <= 1e-9
+    assert np.abs(sg - so).max() <= 1e-9
+    assert rel_max(bg, bo) <= 1e-9
+    # the first solve is tight (eta_0 = 1e-4), so both sides reach nearly the
+    # same first iterate and compute nearly the same eta_1 (a loose first solve
+    # makes the iterate depend on where GMRES happened to stop)
+    eg = sim_eta
+    eo = rep[0]["eta"] if info["substeps"] == len(rep) == 1 else None
+    assert eg[0] == 1e-4
+    if eo is not None:
+        assert abs(eg[1] - eo[1]) <= 1e-2 * eo[1]
+    # the Newton paths are inexact (eta up to 0.9), so counts agree only roughly
+    no = sum(r["newton"] for r in rep)
+    assert abs(info["newton_iters"] - no) <= max(3, 0.3 * no)
+
+
+@pytest.mark.parametrize("choice", [1, 2])
+def test_adaptive_forcing_affine_floor(choice):
+    """On an affine residual, b(x^1) - r^0 vanishes and ||b(x^1)|| = ||r^0||, so
+    choices 1 and 2 of Eq. (13) give the floor eta_min at the second iteration."""
+    from paper_1808_04338_amd import Sim
+
+    m = synth.model_small()
+    m["sw0"][:] = 0.9
+    m["c_w"] = m["c_o"] = 0.0
+    m["gravity"] = 0.0
+    sim = Sim(m, precision="fp64", newton_tol=1e-11, mb_tol=1e-12, forcing=choice, amg_coarse_max=20)
+    sim.timestep(synth.DAY)
+    eta = sim.eta_history()
+    sim.close()
+    assert eta[0] == 0.1 and len(eta) >= 2
+    assert eta[1] == 1e-8
