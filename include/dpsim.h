@@ -221,10 +221,13 @@ dp_status sim_export_ilu(dp_sim *sim, int32_t *perm, int32_t *brow, int32_t *bco
 /* AMG hierarchy sizes: levels, rows[l], nnz[l] (arrays of amg_max_levels). */
 dp_status sim_amg_info(dp_sim *sim, int32_t *levels, int32_t *rows, int64_t *nnz);
 
-/* Linear tolerances eta_l used by the Newton iterations of the last timestep
- * call, in order, across its sub-steps (lin_rtol each when forcing = 0).  Copies
- * at most cap values into eta (host) and stores the full count. */
-dp_status sim_eta_history(dp_sim *sim, double *eta, int32_t cap, int32_t *count);
+/* Linear tolerances of the Newton iterations of the last timestep call, in
+ * order, across its sub-steps and retries: five doubles per iteration, rec[5i..]
+ * = (eta_l, ||b_l||, ||r_l||, ||b_l - r_{l-1}||, l) with the norms of the
+ * forcing terms (zero when forcing = 0, where eta_l = lin_rtol) and l the
+ * iteration's index within its Newton solve.  Copies at most cap records into
+ * rec (host) and stores the full count. */
+dp_status sim_eta_history(dp_sim *sim, double *rec, int32_t cap, int32_t *count);
 
 /* Setup statistics since sim_create: the number of AMG products (interpolation
  * or Galerkin, one per level and setup) that had a row too long for the

@@ -374,29 +374,32 @@ void launch_assemble(dp_sim* s, double dt) {
 //   CNV = max over node rows of |R_a| dt / (rho_a,ref V phi), control rows |R| *
 //         well_scale (NaN counts as +inf)
 //   sums over node rows of R_o and R_w (for the material-balance measure)
-// Block partials, then the last block combines them in block order.
+// Block partials (grid-stride loop, fixed order), then one block combines them
+// in block order in a second kernel (the kernel boundary orders the partials).
 // ---------------------------------------------------------------------------
+constexpr int RN_BLOCKS = 1024;
+
 __global__ void resnorm_kernel(const d2* __restrict__ R, const double* __restrict__ pvf,
                                const double* __restrict__ pvm, const int* __restrict__ fcell,
                                const double* __restrict__ well_scale, int n, int nw, double dt,
-                               double rho_o, double rho_w, double* part, unsigned int* count,
-                               double* out) {
+                               double rho_o, double rho_w, double* part) {
     __shared__ double sh[3][256 / WAVE];
-    __shared__ bool last;
-    int r = blockIdx.x * blockDim.x + threadIdx.x;
     double v = 0.0, so = 0.0, sw = 0.0;
-    if (r < 2 * n) {
-        double pv = r < n ? pvm[r] : pvf[fcell[r - n]];
-        d2 x = R[r];
-        double a = fabs(x.x) * dt / (rho_o * pv);
-        double b = fabs(x.y) * dt / (rho_w * pv);
-        v = fmax(a, b);
-        if (!(a == a) || !(b == b)) v = INFINITY;
-        so = x.x;
-        sw = x.y;
-    } else if (r < 2 * n + nw) {
-        double a = fabs(R[r].x) * well_scale[r - 2 * n];
-        v = (a == a) ? a : INFINITY;
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < 2 * n + nw; r += gridDim.x * blockDim.x) {
+        if (r < 2 * n) {
+            double pv = r < n ? pvm[r] : pvf[fcell[r - n]];
+            d2 x = R[r];
+            double a = fabs(x.x) * dt / (rho_o * pv);
+            double b = fabs(x.y) * dt / (rho_w * pv);
+            double c = fmax(a, b);
+            if (!(a == a) || !(b == b)) c = INFINITY;
+            v = fmax(v, c);
+            so += x.x;
+            sw += x.y;
+        } else {
+            double a = fabs(R[r].x) * well_scale[r - 2 * n];
+            v = fmax(v, (a == a) ? a : INFINITY);
+        }
     }
     v = wave_max(v);
     so = wave_sum(so);
@@ -417,15 +420,13 @@ __global__ void resnorm_kernel(const d2* __restrict__ R, const double* __restric
         part[3 * (int64_t)blockIdx.x] = m;
         part[3 * (int64_t)blockIdx.x + 1] = a;
         part[3 * (int64_t)blockIdx.x + 2] = b;
-        __threadfence();
-        unsigned int ticket = atomicAdd(count, 1u);
-        last = (ticket == gridDim.x - 1);
     }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
+}
+
+__global__ void resnorm_final(const double* __restrict__ part, int nblk, double* out) {
+    __shared__ double sh[3][256 / WAVE];
     double m = 0.0, a = 0.0, b = 0.0;
-    for (int i = threadIdx.x; i < (int)gridDim.x; i += blockDim.x) {
+    for (int i = threadIdx.x; i < nblk; i += blockDim.x) {
         m = fmax(m, part[3 * (int64_t)i]);
         a += part[3 * (int64_t)i + 1];
         b += part[3 * (int64_t)i + 2];
@@ -433,7 +434,6 @@ __global__ void resnorm_kernel(const d2* __restrict__ R, const double* __restric
     m = wave_max(m);
     a = wave_sum(a);
     b = wave_sum(b);
-    __syncthreads();
     if (threadIdx.x % WAVE == 0) {
         sh[0][threadIdx.x / WAVE] = m;
         sh[1][threadIdx.x / WAVE] = a;
@@ -450,17 +450,16 @@ __global__ void resnorm_kernel(const d2* __restrict__ R, const double* __restric
         out[0] = mm;
         out[1] = aa;
         out[2] = bb;
-        *count = 0u;
     }
 }
 
 ResNorm residual_norm(dp_sim* s, double dt) {
     Topo& t = s->topo;
-    int nblk = ceil_div(2 * t.n + t.nw, 256);
+    int nblk = std::min(ceil_div(2 * t.n + t.nw, 256), RN_BLOCKS);
     if (3 * nblk > 32 * s->red_blocks) fail(DP_E_INVALID, "reduction buffer too small");
     resnorm_kernel<<<nblk, 256, 0, s->stream>>>(s->res, t.pvf, t.pvm, t.fcell, t.well_scale, t.n,
-                                                t.nw, dt, s->rho_o_ref, s->rho_w_ref, s->red_part,
-                                                s->red_count, s->red_out);
+                                                t.nw, dt, s->rho_o_ref, s->rho_w_ref, s->red_part);
+    resnorm_final<<<1, 256, 0, s->stream>>>(s->red_part, nblk, s->red_out);
     DP_LAUNCH_CHECK();
     DP_HIP(hipMemcpyAsync(s->red_host, s->red_out, 3 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
     DP_HIP(hipStreamSynchronize(s->stream));

@@ -1,8 +1,9 @@
 // Vector kernels of the GMRES iteration: classical Gram-Schmidt passes fused
 // with their dot products, norms, the solution update, and precision casts.
 //
-// Reductions are deterministic: every block writes its partial sums, and the
-// last block to finish (ticket counter) adds them in block order.
+// Reductions are deterministic: every block writes its partial sums in a fixed
+// order, and a one-block kernel adds them in block order (the kernel boundary
+// orders the partials; no fences or counters across the chip).
 #include "kernels.h"
 
 namespace dp {
@@ -35,9 +36,8 @@ __device__ inline double block_sum(double v, double* sh) {
 template <int OP, int NV>
 __global__ void __launch_bounds__(RBLK) red_kernel(const double* __restrict__ V, int64_t ld, int nv,
                                                    const double* __restrict__ h, double* w, int64_t len,
-                                                   double* part, unsigned int* count, double* out) {
+                                                   double* part) {
     __shared__ double sh[NV][RBLK / WAVE];
-    __shared__ bool last;
     double acc[NV];
     double hh[NV];
 #pragma unroll
@@ -102,21 +102,20 @@ __global__ void __launch_bounds__(RBLK) red_kernel(const double* __restrict__ V,
 #pragma unroll
         for (int q = 0; q < RBLK / WAVE; ++q) b += sh[threadIdx.x][q];
         part[(int64_t)blockIdx.x * KMAX + threadIdx.x] = b;
-        __threadfence();
     }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned int ticket = atomicAdd(count, 1u);
-        last = (ticket == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-    // last block: thread t adds the partials of blocks t, t + RBLK, ... for every
-    // result (independent loads), then one block reduction per result
+}
+
+// out[k] = sum over the nblk block partials of result k, for k < nres: thread t
+// adds blocks t, t + RBLK, ... (independent loads), then a block reduction.
+template <int NV>
+__global__ void __launch_bounds__(RBLK) red_final(const double* __restrict__ part, int nblk, int nres,
+                                                  double* out) {
+    __shared__ double sh[NV][RBLK / WAVE];
+    const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
+    double acc[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) acc[k] = 0.0;
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += RBLK) {
+    for (int b = threadIdx.x; b < nblk; b += RBLK) {
 #pragma unroll
         for (int k = 0; k < NV; ++k)
             if (k < nres) acc[k] += part[(int64_t)b * KMAX + k];
@@ -135,7 +134,6 @@ __global__ void __launch_bounds__(RBLK) red_kernel(const double* __restrict__ V,
         for (int q = 0; q < RBLK / WAVE; ++q) v += sh[threadIdx.x][q];
         out[threadIdx.x] = v;
     }
-    if (threadIdx.x == 0) *count = 0u;
 }
 
 static int red_grid(int64_t len) {
@@ -148,7 +146,8 @@ static int red_grid(int64_t len) {
 template <int OP, int NV>
 static void red_go(dp_sim* s, int g, const double* V, int64_t ld, int nv, const double* h, double* w,
                    int64_t len, double* out) {
-    red_kernel<OP, NV><<<g, RBLK, 0, s->stream>>>(V, ld, nv, h, w, len, s->red_part, s->red_count, out);
+    red_kernel<OP, NV><<<g, RBLK, 0, s->stream>>>(V, ld, nv, h, w, len, s->red_part);
+    red_final<NV><<<1, RBLK, 0, s->stream>>>(s->red_part, g, (OP == 0 || OP == 1) ? nv : 1, out);
 }
 
 template <int OP>

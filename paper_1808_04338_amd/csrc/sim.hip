@@ -610,7 +610,7 @@ static bool newton_loop(dp_sim* s, double h, int* newton_its, int* lin_its, doub
         if (!finite(nrm)) return false;
         if (converged(s, nrm)) return true;
         if (it == d.max_newton) break;
-        double eta = d.lin_rtol, nb = 0;
+        double eta = d.lin_rtol, nb = 0, nd = 0;
         if (d.forcing) {
             nb = dev_norm(s, (const double*)s->res);
             if (!have_prev) {
@@ -620,7 +620,7 @@ static bool newton_loop(dp_sim* s, double h, int* newton_its, int* lin_its, doub
                 double* dvec = (double*)s->fu;
                 vec_copy(s, (const double*)s->res, dvec, len);
                 vec_axpy(s, -1.0, (const double*)s->ft, dvec, len);
-                double nd = dev_norm(s, dvec);
+                nd = dev_norm(s, dvec);
                 eta = forcing_term(d, eta_prev, nb, nb_prev, nr_prev, nd);
             }
         }
@@ -631,7 +631,8 @@ static bool newton_loop(dp_sim* s, double h, int* newton_its, int* lin_its, doub
             if (e.code != DP_E_NUMERIC) throw;
             return false;
         }
-        s->eta_hist.push_back(eta);
+        size_t rec = s->eta_hist.size();
+        s->eta_hist.insert(s->eta_hist.end(), {eta, nb, 0.0, nd, (double)it});
         int li = 0;
         double rr = 0;
         int st = solve(s, eta, d.lin_maxit, &li, &rr);
@@ -643,6 +644,7 @@ static bool newton_loop(dp_sim* s, double h, int* newton_its, int* lin_its, doub
             vec_copy(s, (const double*)s->res, (double*)s->ft, len);
             vec_axpy(s, 1.0, (const double*)s->fu, (double*)s->ft, len);
             nr_prev = dev_norm(s, (const double*)s->ft);
+            s->eta_hist[rec + 2] = nr_prev;
             nb_prev = nb;
             eta_prev = eta;
             have_prev = true;
@@ -1268,10 +1270,10 @@ dp_status sim_amg_info(dp_sim* sim, int32_t* levels, int32_t* rows, int64_t* nnz
     return DP_OK;
 }
 
-dp_status sim_eta_history(dp_sim* sim, double* eta, int32_t cap, int32_t* count) {
-    if (!sim || cap < 0 || (cap > 0 && !eta)) return DP_E_INVALID;
-    int32_t n = (int32_t)sim->eta_hist.size();
-    for (int32_t i = 0; i < n && i < cap; ++i) eta[i] = sim->eta_hist[i];
+dp_status sim_eta_history(dp_sim* sim, double* rec, int32_t cap, int32_t* count) {
+    if (!sim || cap < 0 || (cap > 0 && !rec)) return DP_E_INVALID;
+    int32_t n = (int32_t)(sim->eta_hist.size() / 5);
+    for (int32_t i = 0; i < 5 * n && i < 5 * cap; ++i) rec[i] = sim->eta_hist[i];
     if (count) *count = n;
     return DP_OK;
 }

@@ -228,12 +228,13 @@ class Sim:
         return ms.value, n.value, b.value
 
     def eta_history(self):
-        """Linear tolerances of the last timestep's Newton iterations."""
+        """Records (eta, ||b||, ||r||, ||b - r_prev||, l) of the last timestep's
+        Newton iterations, shape (iterations, 5)."""
         n = C.c_int32()
         self._chk(self.lib.sim_eta_history(self.h, None, 0, C.byref(n)))
-        out = np.zeros(max(n.value, 1))
+        out = np.zeros(5 * max(n.value, 1))
         self._chk(self.lib.sim_eta_history(self.h, _dp(out), n.value, C.byref(n)))
-        return out[:n.value].copy()
+        return out[:5 * n.value].reshape(-1, 5).copy()
 
     def amg_global_sort_products(self):
         """AMG products (one per level and setup) formed by the global sort path."""

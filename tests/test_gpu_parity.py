@@ -293,38 +293,38 @@ def test_error_paths():
 
 @pytest.mark.parametrize("choice", [1, 2, 3])
 def test_adaptive_forcing_matches_oracle(choice):
-    """Eq. (13) forcing terms: one 5-day step of the 1,200-DOF model with a
-    multi-level (inexact) AMG on both sides.  The GPU and oracle reach the same
-    converged state and compute the same tolerance after the first iteration."""
+    """Eq. (13) forcing terms on one 1-day step of the 1,200-DOF model with a
+    multi-level (inexact) AMG.  Every tolerance the device chose equals the
+    oracle's forcing_term evaluated on the device's own norms, and the converged
+    state equals the oracle's.  (The Newton paths themselves differ: at loose
+    tolerances the iterates depend on where GMRES stopped.)"""
     from paper_1808_04338_amd import Sim
 
     m = synth.model_small()
-    dt = 5.0 * synth.DAY
-    sim = Sim(m, precision="fp64", newton_tol=1e-10, forcing=choice, forcing_eta0=1e-4, amg_coarse_max=20,
-              max_newton=40)
+    dt = 1.0 * synth.DAY
+    # enough iterations that neither side cuts the step (sub-steps change the answer)
+    sim = Sim(m, precision="fp64", newton_tol=1e-10, forcing=choice, amg_coarse_max=20, max_newton=200)
     info = sim.timestep(dt)
+    assert info["cuts"] == 0
     pg, sg, bg = sim.get_state()
-    sim_eta = sim.eta_history()
+    hist = sim.eta_history()
     sim.close()
+    assert len(hist) >= 3
+    for k, (eta, nb, nr, nd, it) in enumerate(hist):
+        if it == 0:
+            assert eta == 0.1
+            continue
+        e_prev, nb_prev, nr_prev = hist[k - 1][0], hist[k - 1][1], hist[k - 1][2]
+        want = onewton.forcing_term(choice, e_prev, nb, nb_prev, nr_prev, nd)
+        assert abs(eta - want) <= 1e-13 * want
     geo = oph.Geometry(m)
     x, rep, _ = onewton.timestep(geo, oph.initial_state(m), dt, controls(m), tol=1e-10, linear="cpr",
-                                 forcing=choice, eta0=1e-4, max_newton=40,
-                                 cpr_opts=dict(amg_opts=dict(max_coarse=20)))
+                                 forcing=choice, max_newton=200, cpr_opts=dict(amg_opts=dict(max_coarse=20)))
+    assert len(rep) == 1
     po, so, bo = oph.unpack_state(x, geo.n)
     assert rel_max(pg, po) <= 1e-9
     assert np.abs(sg - so).max() <= 1e-9
     assert rel_max(bg, bo) <= 1e-9
-    # the first solve is tight (eta_0 = 1e-4), so both sides reach nearly the
-    # same first iterate and compute nearly the same eta_1 (a loose first solve
-    # makes the iterate depend on where GMRES happened to stop)
-    eg = sim_eta
-    eo = rep[0]["eta"] if info["substeps"] == len(rep) == 1 else None
-    assert eg[0] == 1e-4
-    if eo is not None:
-        assert abs(eg[1] - eo[1]) <= 1e-2 * eo[1]
-    # the Newton paths are inexact (eta up to 0.9), so counts agree only roughly
-    no = sum(r["newton"] for r in rep)
-    assert abs(info["newton_iters"] - no) <= max(3, 0.3 * no)
 
 
 @pytest.mark.parametrize("choice", [1, 2])
@@ -339,7 +339,7 @@ def test_adaptive_forcing_affine_floor(choice):
     m["gravity"] = 0.0
     sim = Sim(m, precision="fp64", newton_tol=1e-11, mb_tol=1e-12, forcing=choice, amg_coarse_max=20)
     sim.timestep(synth.DAY)
-    eta = sim.eta_history()
+    hist = sim.eta_history()
     sim.close()
-    assert eta[0] == 0.1 and len(eta) >= 2
-    assert eta[1] == 1e-8
+    assert hist[0][0] == 0.1 and len(hist) >= 2
+    assert hist[1][0] == 1e-8
