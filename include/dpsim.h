@@ -244,6 +244,10 @@ dp_status sim_export_amg_level(dp_sim *sim, int32_t level, int32_t *cf, int32_t 
                                int32_t *a_col, double *a_val, int32_t *p_rowptr, int32_t *p_col,
                                double *p_val, int64_t *p_nnz);
 
+/* The correction y of the last krylov_solve (solution of J y = -R through the
+ * decoupled system), host vector [n_dof] in canonical order.  Synchronises. */
+dp_status sim_get_correction(dp_sim *sim, double *dx);
+
 /* z = M^-1 r (CPR-FPF) and y = A x (decoupled matrix), host vectors in
  * canonical order [n_dof].  After cpr_fpf_setup. */
 dp_status sim_apply_precond(dp_sim *sim, const double *r, double *z);

@@ -91,6 +91,7 @@ _SIGS = {
     "sim_amg_info": [C.c_void_p, _iptr, _iptr, _lptr],
     "sim_amg_stats": [C.c_void_p, _lptr],
     "sim_eta_history": [C.c_void_p, _dptr, C.c_int32, _iptr],
+    "sim_get_correction": [C.c_void_p, _dptr],
     "sim_kernel_timer": [C.c_void_p, C.c_int32, C.c_int32],
     "sim_kernel_time": [C.c_void_p, C.c_int32, _dptr, _lptr, _dptr],
     "sim_export_amg_level": [C.c_void_p, C.c_int32, _iptr, _iptr, _iptr, _dptr, _iptr, _iptr, _dptr,

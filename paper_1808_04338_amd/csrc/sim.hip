@@ -1087,6 +1087,16 @@ dp_status sim_get_state(dp_sim* sim, double* p, double* sw, double* bhp) {
     ABI_END(sim)
 }
 
+dp_status sim_get_correction(dp_sim* sim, double* dx) {
+    if (!sim || !dx) return DP_E_INVALID;
+    ABI_BEGIN
+    if (sim->stage < 2) fail(DP_E_STATE, "no correction before krylov_solve");
+    std::vector<d2> xs = dl(sim, sim->dx, sim->topo.nb);
+    from_positions(sim, xs, dx);
+    return DP_OK;
+    ABI_END(sim)
+}
+
 dp_status sim_set_state(dp_sim* sim, const double* p, const double* sw, const double* bhp) {
     if (!sim || !p || !sw) return DP_E_INVALID;
     ABI_BEGIN

@@ -227,6 +227,12 @@ class Sim:
         self._chk(self.lib.sim_kernel_time(self.h, int(kernel), C.byref(ms), C.byref(n), C.byref(b)))
         return ms.value, n.value, b.value
 
+    def get_correction(self):
+        """The last Krylov solution y of J y = -R, canonical order."""
+        y = np.empty(self.n_dof)
+        self._chk(self.lib.sim_get_correction(self.h, _dp(y)))
+        return y
+
     def eta_history(self):
         """Records (eta, ||b||, ||r||, ||b - r_prev||, l) of the last timestep's
         Newton iterations, shape (iterations, 5)."""
