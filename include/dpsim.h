@@ -119,6 +119,11 @@ typedef struct {
     double forcing_beta;      /* [2], in (1, 2] */
     double forcing_eta_min;   /* [1e-8] */
     double forcing_eta_max;   /* [0.9] */
+    int32_t precond_eager;    /* preconditioner apply: 1 launches its kernels one by one; 2 captures
+                                 them into a HIP graph after each setup and replays it on every
+                                 apply; 0 (auto) replays below 1M unknowns, where launches
+                                 dominate, and launches one by one above (the phase timers always
+                                 use the one-by-one path) [0] */
 } dp_sim_desc;
 
 typedef struct {

@@ -633,7 +633,7 @@ void ilu_solve(dp_sim* s, const V2<T>* r, V2<T>* z) {
     Topo& t = s->topo;
     IluSolveArgs<T> a{ilu_args<T>(s), r, z};
     int nb_red = ceil_div(t.nred, 256), nb_black = ceil_div(t.n - t.nred, 256);
-    KtScope ks(&s->kt[1], s->stream);
+    KtScope ks(s->capturing ? nullptr : &s->kt[1], s->stream);
     ks.bytes(kernel_bytes(s, 1));
     if (nb_red) ilus_red_fwd<T><<<nb_red, 256, 0, s->stream>>>(a);
     if (nb_black) ilus_black<T><<<nb_black, 256, 0, s->stream>>>(a);

@@ -173,6 +173,11 @@ struct dp_sim {
     dp::d2* ft = nullptr;       // adaptive forcing: R + J dx of the previous iteration
     dp::d2* fu = nullptr;       // adaptive forcing: work vector
     std::vector<double> eta_hist;  // linear tolerances of the last timestep's Newton iterations
+    // preconditioner apply replayed from a HIP graph (captured after each setup)
+    hipGraphExec_t pc_exec = nullptr;
+    hipStream_t cap_stream = nullptr;  // private stream the capture runs on
+    bool pc_graph_ok = false;
+    bool capturing = false;  // kernel timers stay out of a capture
     double dt_assembled = 0.0;
     int stage = 0;              // 0 nothing, 1 assembled, 2 setup done
 

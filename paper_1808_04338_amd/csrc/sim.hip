@@ -50,6 +50,7 @@ static void validate(const dp_sim_desc& d) {
     if (d.precond_precision != DP_FP64 && d.precond_precision != DP_FP32)
         fail(DP_E_INVALID, "precond_precision must be DP_FP64 or DP_FP32");
     if (d.forcing < 0 || d.forcing > 3) fail(DP_E_INVALID, "forcing must be 0, 1, 2 or 3");
+    if (d.precond_eager < 0 || d.precond_eager > 2) fail(DP_E_INVALID, "precond_eager must be 0, 1 or 2");
     if (d.forcing && !(d.forcing_beta > 1.0 && d.forcing_beta <= 2.0 && d.forcing_gamma <= 1.0 &&
                        d.forcing_eta_min <= d.forcing_eta_max && d.forcing_eta_max < 1.0))
         fail(DP_E_INVALID, "forcing parameters out of range");
@@ -950,6 +951,8 @@ dp_status sim_destroy(dp_sim* sim) {
     for (auto& t : sim->kt)
         for (auto& e : t.ev)
             if (e) (void)hipEventDestroy(e);
+    if (sim->pc_exec) (void)hipGraphExecDestroy(sim->pc_exec);
+    if (sim->cap_stream) (void)hipStreamDestroy(sim->cap_stream);
     delete sim;
     return DP_OK;
 }

@@ -77,6 +77,7 @@ def make_desc(model, precision=None, **opts):
     d.forcing_beta = float(opts.get("forcing_beta", 2.0))
     d.forcing_eta_min = float(opts.get("forcing_eta_min", 1e-8))
     d.forcing_eta_max = float(opts.get("forcing_eta_max", 0.9))
+    d.precond_eager = int(opts.get("precond_eager", 0))
     return d, keep
 
 
