@@ -43,19 +43,42 @@ from . import physics as ph
 # Decoupling
 # --------------------------------------------------------------------------
 
-def decouple(n_nodes, indptr, indices, data, b):
-    """Apply D^-1 to the block matrix (indptr, indices, data) and to b."""
+DECOUPLINGS = ("gj", "abf", "ti")
+
+
+def decouple(n_nodes, indptr, indices, data, b, variant="gj"):
+    """Apply D^-1 to the block matrix (indptr, indices, data) and to b (Eq. (14)).
+
+    Every node row i is multiplied by a 2x2 matrix Q_i = D_i^-1 (well rows are
+    left as they are):
+      'gj'  one Gauss-Jordan step with a = J_ii: Q = [[1, -a01/a11], [0, 1]]
+            (the reading of the paper's modified Gauss-Jordan decoupling);
+      'abf' alternate block factorisation: Q = J_ii^-1, so that every diagonal
+            block becomes the identity;
+      'ti'  true-IMPES weights: Q = [[1, -c01/c11], [0, 1]] with c the sum of the
+            row's blocks, so that the pressure row's saturation coefficients sum
+            to zero over the row.
+    """
     nb = indptr.shape[0] - 1
     rows = np.repeat(np.arange(nb), np.diff(indptr))
     diag_pos = np.empty(nb, dtype=np.int64)
     diag_pos[rows[indices == rows]] = np.nonzero(indices == rows)[0]
     a = data[diag_pos]
-    f = np.zeros(nb)
-    f[:n_nodes] = a[:n_nodes, 0, 1] / a[:n_nodes, 1, 1]
-    out = data.copy()
-    out[:, 0, :] = data[:, 0, :] - f[rows][:, None] * data[:, 1, :]
-    bh = b.copy()
-    bh[0::2] = b[0::2] - f * b[1::2]
+    Q = np.zeros((nb, 2, 2))
+    Q[:, 0, 0] = Q[:, 1, 1] = 1.0
+    nd = slice(0, n_nodes)
+    if variant == "gj":
+        Q[nd, 0, 1] = -a[nd, 0, 1] / a[nd, 1, 1]
+    elif variant == "abf":
+        Q[nd] = np.linalg.inv(a[nd])
+    elif variant == "ti":
+        c = np.zeros((nb, 2, 2))
+        np.add.at(c, rows, data)
+        Q[nd, 0, 1] = -c[nd, 0, 1] / c[nd, 1, 1]
+    else:
+        raise ValueError("unknown decoupling %r" % (variant,))
+    out = np.einsum("rij,rjk->rik", Q[rows], data)
+    bh = np.einsum("rij,rj->ri", Q, b.reshape(nb, 2)).reshape(-1)
     return out, bh
 
 
@@ -374,8 +397,11 @@ class AMG:
 class CPRFPF:
     """CPR-FPF preconditioner for the decoupled block matrix."""
 
-    def __init__(self, geo, indptr, indices, data, perm=None, amg_opts=None, exact_f=False):
+    def __init__(self, geo, indptr, indices, data, perm=None, amg_opts=None, exact_f=False, variant="fpf"):
         nb = indptr.shape[0] - 1
+        if variant not in ("fpf", "fp"):
+            raise ValueError("unknown CPR variant %r" % (variant,))
+        self.variant = variant
         self.A = ph.bsr_to_csr(indptr, indices, data)
         self.perm = default_ordering(geo) if perm is None else perm
         if exact_f:
@@ -406,8 +432,14 @@ class CPRFPF:
         return e
 
     def apply(self, r):
-        z = self.fsolve(r)
-        res = r - self.A @ z
+        """'fpf': z1 = F^-1 r; z2 = z1 + R^T Mp^-1 R (r - A z1); z = z2 + F^-1 (r - A z2).
+        'fp' (two-stage, pressure first): z1 = R^T Mp^-1 R r; z = z1 + F^-1 (r - A z1)."""
+        if self.variant == "fpf":
+            z = self.fsolve(r)
+            res = r - self.A @ z
+        else:
+            z = np.zeros_like(r)
+            res = r
         e = self.pressure_solve(res[0::2])
         z = z.copy()
         z[0::2] += e
@@ -479,11 +511,12 @@ def gmres(matvec, precond, b, rtol, restart=30, maxit=300, x0=None, trace=None):
     return x, its, beta / bnorm
 
 
-def solve(geo, J, rhs, rtol=1e-6, restart=30, maxit=300, amg_opts=None, exact_f=False):
-    """Solve J y = rhs: decouple, build CPR-FPF, run GMRES on the decoupled
-    system.  Returns (y, iterations, relative decoupled residual)."""
+def solve(geo, J, rhs, rtol=1e-6, restart=30, maxit=300, amg_opts=None, exact_f=False, decoupling="gj",
+          variant="fpf"):
+    """Solve J y = rhs: decouple, build CPR-FPF (or CPR-FP), run GMRES on the
+    decoupled system.  Returns (y, iterations, relative decoupled residual)."""
     indptr, indices, data = ph.to_bsr(geo, J)
-    dh, bh = decouple(2 * geo.n, indptr, indices, data, rhs)
-    pc = CPRFPF(geo, indptr, indices, dh, amg_opts=amg_opts, exact_f=exact_f)
+    dh, bh = decouple(2 * geo.n, indptr, indices, data, rhs, decoupling)
+    pc = CPRFPF(geo, indptr, indices, dh, amg_opts=amg_opts, exact_f=exact_f, variant=variant)
     y, its, rel = gmres(lambda v: pc.A @ v, pc.apply, bh, rtol, restart, maxit)
     return y, its, rel

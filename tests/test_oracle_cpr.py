@@ -278,3 +278,67 @@ def test_reduced_pressure_solve_is_exact_with_one_level():
     assert np.array_equal(blk.indptr, pc.S.indptr) and np.array_equal(blk.indices, pc.S.indices)
     off = blk.indices != np.repeat(np.arange(blk.shape[0]), np.diff(blk.indptr))
     assert np.array_equal(blk.data[off], pc.S.data[off])
+
+
+def test_abf_decoupling_makes_node_diagonal_blocks_the_identity():
+    geo, J, b = _system(synth.model_small())
+    indptr, indices, data = ph.to_bsr(geo, J)
+    dh, _ = cpr.decouple(2 * geo.n, indptr, indices, data, b, "abf")
+    nb = indptr.shape[0] - 1
+    rows = np.repeat(np.arange(nb), np.diff(indptr))
+    sel = (indices == rows) & (rows < 2 * geo.n)
+    d = dh[sel]
+    # the blocks mix units (Pa and saturation): each entry is judged against the
+    # magnitudes the product combined, (|a^-1| |a|)_ij
+    a = data[sel]
+    scale = np.einsum("rij,rjk->rik", np.abs(np.linalg.inv(a)), np.abs(a))
+    assert np.max(np.abs(d - np.eye(2)) / scale) <= 1e-12
+
+
+def test_true_impes_pressure_row_has_zero_saturation_column_sum():
+    """The weights cancel the sum over the row of the saturation coefficients."""
+    geo, J, b = _system(synth.model_small())
+    indptr, indices, data = ph.to_bsr(geo, J)
+    dh, _ = cpr.decouple(2 * geo.n, indptr, indices, data, b, "ti")
+    nb = indptr.shape[0] - 1
+    rows = np.repeat(np.arange(nb), np.diff(indptr))
+    s = np.zeros(nb)
+    a = np.zeros(nb)
+    np.add.at(s, rows, dh[:, 0, 1])
+    np.add.at(a, rows, np.abs(data[:, 0, 1]) + np.abs(data[:, 1, 1]))
+    nd = slice(0, 2 * geo.n)
+    assert np.max(np.abs(s[nd]) / a[nd]) <= 1e-12
+
+
+@pytest.mark.parametrize("variant", ["gj", "abf", "ti"])
+def test_decoupled_system_has_the_same_solution(variant):
+    """D is invertible: D^-1 J y = D^-1 b has the solution of J y = b."""
+    geo, J, b = _system(synth.model_small())
+    indptr, indices, data = ph.to_bsr(geo, J)
+    dh, bh = cpr.decouple(2 * geo.n, indptr, indices, data, b, variant)
+    Ah = ph.bsr_to_csr(indptr, indices, dh)
+    y0 = spla.spsolve(J.tocsc(), b)
+    y1 = spla.spsolve(Ah.tocsc(), bh)
+    # the same D^-1 on both sides: the original solution leaves a rounding-level
+    # residual in the decoupled system; the two direct solutions differ by about
+    # kappa * eps (the system is badly scaled: Pa against saturation)
+    res = Ah @ y0 - bh
+    assert np.linalg.norm(res) <= 1e-10 * np.linalg.norm(abs(Ah) @ np.abs(y0) + np.abs(bh))
+    assert np.abs(y1 - y0).max() <= 1e-6 * np.abs(y0).max()
+
+
+def test_cpr_fp_with_exact_full_stage_converges_in_one_iteration():
+    """Two-stage CPR-FP: z1 = R^T Mp^-1 R r, z = z1 + F^-1 (r - A z1); with F
+    exact the second stage alone solves the system."""
+    geo, J, b = _system(synth.model_small())
+    y, its, rel = cpr.solve(geo, J, b, rtol=1e-10, exact_f=True, variant="fp")
+    assert its == 1 and rel <= 1e-10
+
+
+@pytest.mark.parametrize("decoupling,variant", [("abf", "fpf"), ("ti", "fpf"), ("gj", "fp"), ("abf", "fp")])
+def test_cpr_variants_reach_the_direct_solution(decoupling, variant):
+    geo, J, b = _system(synth.model_small())
+    y, its, rel = cpr.solve(geo, J, b, rtol=1e-10, decoupling=decoupling, variant=variant)
+    y0 = spla.spsolve(J.tocsc(), b)
+    assert rel <= 1e-10
+    assert np.abs(y - y0).max() <= 1e-6 * np.abs(y0).max()
