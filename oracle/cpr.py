@@ -46,18 +46,19 @@ from . import physics as ph
 DECOUPLINGS = ("gj", "abf", "ti")
 
 
-def decouple(n_nodes, indptr, indices, data, b, variant="gj"):
-    """Apply D^-1 to the block matrix (indptr, indices, data) and to b (Eq. (14)).
+def decoupling_operator(n_nodes, indptr, indices, data, variant="gj"):
+    """The 2x2 matrix Q_i = D_i^-1 of every block row (Sec. 3.2, Eq. (14)); the
+    identity on well rows.
 
-    Every node row i is multiplied by a 2x2 matrix Q_i = D_i^-1 (well rows are
-    left as they are):
       'gj'  one Gauss-Jordan step with a = J_ii: Q = [[1, -a01/a11], [0, 1]]
-            (the reading of the paper's modified Gauss-Jordan decoupling);
+            (the reading of the paper's modified Gauss-Jordan decoupling; for
+            2x2 blocks it is also the Quasi-IMPES operator, whose weights come
+            from the diagonal block);
       'abf' alternate block factorisation: Q = J_ii^-1, so that every diagonal
             block becomes the identity;
-      'ti'  true-IMPES weights: Q = [[1, -c01/c11], [0, 1]] with c the sum of the
-            row's blocks, so that the pressure row's saturation coefficients sum
-            to zero over the row.
+      'ti'  true-IMPES: Q = [[1, -c01/c11], [0, 1]] with c_i the sum of block
+            column i, sum_k J_ki.  Conservative fluxes cancel in a column sum,
+            so c_i holds the accumulation (and well) derivatives of node i.
     """
     nb = indptr.shape[0] - 1
     rows = np.repeat(np.arange(nb), np.diff(indptr))
@@ -73,10 +74,19 @@ def decouple(n_nodes, indptr, indices, data, b, variant="gj"):
         Q[nd] = np.linalg.inv(a[nd])
     elif variant == "ti":
         c = np.zeros((nb, 2, 2))
-        np.add.at(c, rows, data)
+        np.add.at(c, indices, data)
         Q[nd, 0, 1] = -c[nd, 0, 1] / c[nd, 1, 1]
     else:
         raise ValueError("unknown decoupling %r" % (variant,))
+    return Q
+
+
+def decouple(n_nodes, indptr, indices, data, b, variant="gj"):
+    """Apply D^-1 to the block matrix (indptr, indices, data) and to b (Eq. (14)):
+    every block row i is multiplied by Q_i of decoupling_operator."""
+    nb = indptr.shape[0] - 1
+    rows = np.repeat(np.arange(nb), np.diff(indptr))
+    Q = decoupling_operator(n_nodes, indptr, indices, data, variant)
     out = np.einsum("rij,rjk->rik", Q[rows], data)
     bh = np.einsum("rij,rj->ri", Q, b.reshape(nb, 2)).reshape(-1)
     return out, bh

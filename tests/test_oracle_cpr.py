@@ -295,19 +295,38 @@ def test_abf_decoupling_makes_node_diagonal_blocks_the_identity():
     assert np.max(np.abs(d - np.eye(2)) / scale) <= 1e-12
 
 
-def test_true_impes_pressure_row_has_zero_saturation_column_sum():
-    """The weights cancel the sum over the row of the saturation coefficients."""
-    geo, J, b = _system(synth.model_small())
+def test_true_impes_weights_are_the_density_ratio():
+    """Fluxes between nodes (faces and matrix-fracture transfer) are
+    conservative, so they cancel in a block column sum; what is left in the
+    column of a node without a perforation is its accumulation derivative,
+    d/dS_w of (V phi (1 - S_w) rho_o, V phi S_w rho_w) / dt, and the true-IMPES
+    weight Q01 = -c01/c11 is rho_o(p)/rho_w(p) at that node: the pressure row
+    becomes the volume balance R_o/rho_o + R_w/rho_w, scaled by rho_o.  Judged against
+    the rounding of the column sums, sum_k |J_ki| / |c_i|."""
+    m = synth.model_small()
+    geo, J, b = _system(m, seed=4)
     indptr, indices, data = ph.to_bsr(geo, J)
-    dh, _ = cpr.decouple(2 * geo.n, indptr, indices, data, b, "ti")
+    Q = cpr.decoupling_operator(2 * geo.n, indptr, indices, data, "ti")
+    p, _, _ = ph.unpack_state(ph.pack_state(*synth.random_state(m, 4)), geo.n)
+    rho_o, _ = ph.density(p, m["rho_o_ref"], m["c_o"], m["p_ref"])
+    rho_w, _ = ph.density(p, m["rho_w_ref"], m["c_w"], m["p_ref"])
     nb = indptr.shape[0] - 1
-    rows = np.repeat(np.arange(nb), np.diff(indptr))
-    s = np.zeros(nb)
-    a = np.zeros(nb)
-    np.add.at(s, rows, dh[:, 0, 1])
-    np.add.at(a, rows, np.abs(data[:, 0, 1]) + np.abs(data[:, 1, 1]))
-    nd = slice(0, 2 * geo.n)
-    assert np.max(np.abs(s[nd]) / a[nd]) <= 1e-12
+    absum = np.zeros((nb, 2, 2))
+    csum = np.zeros((nb, 2, 2))
+    np.add.at(absum, indices, np.abs(data))
+    np.add.at(csum, indices, data)
+    perforated = np.zeros(2 * geo.n, dtype=bool)
+    for cells, _ in geo.perfs:
+        perforated[2 * cells] = True  # wells perforate fracture nodes
+    free = ~perforated
+    assert free.sum() > geo.n
+    w = Q[:2 * geo.n, 0, 1]
+    bound = 1e-13 * (absum[:2 * geo.n, 0, 1] / np.abs(csum[:2 * geo.n, 0, 1])
+                     + absum[:2 * geo.n, 1, 1] / np.abs(csum[:2 * geo.n, 1, 1]))
+    ratio = rho_o / rho_w
+    assert np.all(np.abs(w[free] - ratio[free]) <= bound[free] * ratio[free])
+    # at perforated nodes the well terms do not cancel: the weight differs
+    assert np.abs(w[perforated] - ratio[perforated]).max() > 1e-6
 
 
 @pytest.mark.parametrize("variant", ["gj", "abf", "ti"])
