@@ -206,6 +206,27 @@ def forcing_study(steps):
     return out
 
 
+def precond_study(nz, steps, rtol):
+    """Each decoupling of Sec. 3.2 (Gauss-Jordan, ABF, true-IMPES) with each
+    composition (FPF, FP): the benchmarked solve (the third Newton iterate of the
+    first step of the 60x220xnz model, FP32 preconditioner, GMRES to rtol), the
+    same state for every combination.  One record per combination."""
+    model = make_model(nz)
+    out = []
+    state = None
+    for dec in ("gj", "abf", "ti"):
+        for cpr in ("fpf", "fp"):
+            r, state = timed_form(model, "fp32", steps, 1, rtol, state=state, kernels=False, decoupling=dec,
+                                  cpr_variant=cpr)
+            rec = dict(decoupling=dec, cpr=cpr, gmres_iters=r["iters"], rel=r["rel"],
+                       solves_per_s=steps / r["wall"], ms_per_solve=1e3 * r["wall"] / steps,
+                       setup_ms=r["phases"]["setup_ms"], solve_ms=r["phases"]["solve_ms"],
+                       precond_ms_total=r["phases"]["precond_ms_total"])
+            out.append(rec)
+            log("%s/%s: %s iterations, %.2f solves/s" % (dec, cpr, r["iters"], rec["solves_per_s"]))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -229,6 +250,9 @@ def main():
     ap.add_argument("--forcing-study", type=int, default=0,
                     help="instead of the benchmark: that many timesteps of the 144k-DOF model with "
                          "each forcing choice of Eq. (13)")
+    ap.add_argument("--precond-study", type=int, default=0,
+                    help="instead of the benchmark: that many timed solves with each decoupling and "
+                         "CPR composition")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -242,6 +266,14 @@ def main():
         print(json.dumps({"study": "inexact-Newton forcing terms (Eq. (13)) vs fixed eta = 1e-6",
                           "workload": "dual-porosity oil-water 60x60x10 layered five-spot, 144,010 DOF, "
                                       "5-day steps, FP32 preconditioner",
+                          "data": "synthetic", "results": rec}))
+        return
+    if args.precond_study > 0:
+        rec = precond_study(args.nz, args.precond_study, args.rtol)
+        print(json.dumps({"study": "decoupling (Gauss-Jordan, ABF, true-IMPES) x CPR composition (FPF, FP)",
+                          "workload": "dual-porosity oil-water 60x220x%d channelised, third Newton iterate of "
+                                      "the first 10-day step, FP32 preconditioner, GMRES to %g"
+                                      % (args.nz, args.rtol),
                           "data": "synthetic", "results": rec}))
         return
     log("generating the 60x220x%d model" % args.nz)

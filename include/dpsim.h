@@ -55,6 +55,17 @@ enum {
 enum { DP_WELL_INJ = 0, DP_WELL_PROD = 1 };   /* water injector | producer */
 enum { DP_CTRL_RATE = 0, DP_CTRL_BHP = 1 };   /* control equation of a well */
 enum { DP_FP64 = 0, DP_FP32 = 1 };            /* preconditioner precision */
+/* Decoupling D^-1 of Eq. (14), per node row (Sec. 3.2): DP_DEC_GJ one
+ * Gauss-Jordan step on the diagonal block (row0 -= a01/a11 row1; for 2x2 blocks
+ * this is also the Quasi-IMPES operator); DP_DEC_ABF alternate block
+ * factorisation, the inverse of the diagonal block; DP_DEC_TI true-IMPES
+ * (row0 -= c01/c11 row1, c_i the sum of block column i, where the fluxes
+ * cancel).  Well rows are not changed. */
+enum { DP_DEC_GJ = 0, DP_DEC_ABF = 1, DP_DEC_TI = 2 };
+/* CPR composition with F = block ILU(0), P = pressure stage: FPF z1 = F^-1 r,
+ * z2 = z1 + R^T Mp^-1 R (r - A z1), z = z2 + F^-1 (r - A z2); FP (two-stage,
+ * pressure first) z1 = R^T Mp^-1 R r, z = z1 + F^-1 (r - A z1). */
+enum { DP_CPR_FPF = 0, DP_CPR_FP = 1 };
 
 typedef struct dp_sim dp_sim;
 
@@ -124,6 +135,8 @@ typedef struct {
                                  apply; 0 (auto) replays below 1M unknowns, where launches
                                  dominate, and launches one by one above (the phase timers always
                                  use the one-by-one path) [0] */
+    int32_t decoupling;       /* DP_DEC_GJ | DP_DEC_ABF | DP_DEC_TI [DP_DEC_GJ] */
+    int32_t cpr_variant;      /* DP_CPR_FPF | DP_CPR_FP [DP_CPR_FPF] */
 } dp_sim_desc;
 
 typedef struct {

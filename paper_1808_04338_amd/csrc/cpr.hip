@@ -24,15 +24,18 @@ void cpr_setup(dp_sim* s) {
     s->pc_graph_ok = false;  // factors and hierarchy changed: recapture before replaying
 }
 
-// z1 = F^-1 r, pressure stage, z2 = z1 + R^T e, t = r - A z2, z1 = F^-1 t (the
-// caller adds z2 + z1).  Every pointer is fixed between setups, so the whole
+// FPF: z1 = F^-1 r; FP: z1 = 0.  Then the pressure stage, z2 = z1 + R^T e,
+// t = r - A z2, z1 = F^-1 t (the caller adds z2 + z1).  Every pointer is fixed between setups, so the whole
 // sequence can be captured into a HIP graph when r is the handle's own buffer.
 template <class T>
 static void apply_core(dp_sim* s, const V2<T>* r) {
     V2<T>* z1 = (V2<T>*)s->pz;
     V2<T>* z2 = (V2<T>*)s->pz2;
     V2<T>* t = (V2<T>*)s->pt;
-    ilu_solve<T>(s, r, z1);
+    // FP starts the pressure stage from z1 = 0 (a fill kernel, not a memset:
+    // the sequence may be captured into a graph)
+    if (s->desc.cpr_variant == DP_CPR_FP) vec_fill_zero<T>(s, (T*)z1, 2 * (int64_t)s->topo.nb);
+    else ilu_solve<T>(s, r, z1);
     bresidual_p<T>(s, r, z1, (T*)s->levels[0].b);
     T* e = amg_vcycle<T>(s);
     bresidual_prol<T>(s, r, z1, e, z2, t);

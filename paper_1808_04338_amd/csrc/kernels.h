@@ -29,6 +29,7 @@ void jspmv(dp_sim* s, const d2* x, d2* y);  // y = J x, undecoupled Jacobian
 // ILU(0) solve in the preconditioner precision, 2 AMG V-cycle, 3 assembly).
 double kernel_bytes(dp_sim* s, int kernel);
 void copy_f64(dp_sim* s, const double* x, double* y, int64_t len);
+template <class T> void vec_fill_zero(dp_sim* s, T* x, int64_t len);
 template <class T> void bresidual(dp_sim* s, const V2<T>* b, const V2<T>* x, V2<T>* y);
 template <class T> void bresidual_p(dp_sim* s, const V2<T>* b, const V2<T>* x, T* yp);
 template <class T>

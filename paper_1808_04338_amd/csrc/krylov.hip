@@ -249,6 +249,19 @@ void copy_f64(dp_sim* s, const double* x, double* y, int64_t len) {
     DP_LAUNCH_CHECK();
 }
 
+template <class T>
+__global__ void fill_zero_kernel(T* x, int64_t len) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < len) x[i] = T(0);
+}
+template <class T>
+void vec_fill_zero(dp_sim* s, T* x, int64_t len) {
+    fill_zero_kernel<T><<<ceil_div(len, 256), 256, 0, s->stream>>>(x, len);
+    DP_LAUNCH_CHECK();
+}
+template void vec_fill_zero<float>(dp_sim*, float*, int64_t);
+template void vec_fill_zero<double>(dp_sim*, double*, int64_t);
+
 void vec_copy(dp_sim* s, const double* x, double* y, int64_t len) {
     DP_HIP(hipMemcpyAsync(y, x, sizeof(double) * len, hipMemcpyDeviceToDevice, s->stream));
 }

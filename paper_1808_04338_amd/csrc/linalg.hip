@@ -8,30 +8,44 @@
 namespace dp {
 
 // ---------------------------------------------------------------------------
-// Decoupling D^-1 J, D^-1 b (Eq. (14)): in each node row, row0 -= (a01/a11) row1
-// with a = J_ii.  Well rows are copied.  b = -R.
+// Decoupling D^-1 J, D^-1 b (Eq. (14)): every block of node row i is multiplied
+// by the 2x2 matrix Q = D_i^-1; well rows are copied; b = -R.
+//   DP_DEC_GJ   one Gauss-Jordan step with a = J_ii: Q = [[1, -a01/a11], [0, 1]]
+//   DP_DEC_ABF  alternate block factorisation: Q = J_ii^-1
+//   DP_DEC_TI   true-IMPES: Q = [[1, -c01/c11], [0, 1]], c_i the sum of block column i
+//               (gathered from the transposed positions: a face slot s of row q
+//               is mirrored by slot s^1 of the neighbour's row)
 // ---------------------------------------------------------------------------
 struct DecArgs {
     BMat<double> J, A;
     BMat<float> A32;
     bool f32;
+    int variant;
     const d2* R;
     d2* b;
-    const int* fmask;
+    const unsigned char* fmask;
+    const int* fcol;
+    const int* fcell;
+    const int* frow;
     const int* fperf;
     const int* well_ptr;
     int n, nw;
 };
 
+struct Q2 {
+    double q00, q01, q10, q11;
+};
+
 __device__ inline void dec_pair(const d2* s0, const d2* s1, d2* o0, d2* o1, float2* p0, float2* p1,
-                                int64_t i, double f, bool f32) {
+                                int64_t i, const Q2& q, bool f32) {
     d2 r0 = s0[i], r1 = s1[i];
-    d2 a0 = mk2(r0.x - f * r1.x, r0.y - f * r1.y);
+    d2 a0 = mk2(q.q00 * r0.x + q.q01 * r1.x, q.q00 * r0.y + q.q01 * r1.y);
+    d2 a1 = mk2(q.q10 * r0.x + q.q11 * r1.x, q.q10 * r0.y + q.q11 * r1.y);
     o0[i] = a0;
-    o1[i] = r1;
+    o1[i] = a1;
     if (f32) {
         p0[i] = make_float2((float)a0.x, (float)a0.y);
-        p1[i] = make_float2((float)r1.x, (float)r1.y);
+        p1[i] = make_float2((float)a1.x, (float)a1.y);
     }
 }
 
@@ -47,32 +61,65 @@ __global__ void __launch_bounds__(256) decouple_kernel(DecArgs a, int bm, int bf
         if (pos >= n) return;
         int row = frac ? n + pos : pos;
         d2 d0 = a.J.d0[row], d1 = a.J.d1[row];
-        double f = d0.y / d1.y;
-        dec_pair(a.J.d0, a.J.d1, a.A.d0, a.A.d1, F32P(a.A32.d0), F32P(a.A32.d1), row, f, f32);
+        const int p = frac ? a.fperf[pos] : -1;
+        Q2 q{1.0, 0.0, 0.0, 1.0};
+        if (a.variant == DP_DEC_ABF) {
+            double det = d0.x * d1.y - d0.y * d1.x;
+            q = Q2{d1.y / det, -d0.y / det, -d1.x / det, d0.x / det};
+        } else if (a.variant == DP_DEC_TI) {
+            // saturation column of the block column sum: J_ii plus every block
+            // that couples another row to this node
+            double c01 = d0.y, c11 = d1.y;
+            if (!frac) {
+                int64_t e = (int64_t)6 * n + a.frow[pos];  // matrix slot of its fracture row
+                c01 += a.J.f0[e].y;
+                c11 += a.J.f1[e].y;
+            } else {
+                unsigned mask = a.fmask[pos];
+                for (int s = 0; s < 6; ++s) {
+                    if (!(mask & (1u << s))) continue;
+                    int nq = a.fcol[(int64_t)s * n + pos] - n;
+                    int64_t e = (int64_t)(s ^ 1) * n + nq;
+                    c01 += a.J.f0[e].y;
+                    c11 += a.J.f1[e].y;
+                }
+                int c = a.fcell[pos];
+                c01 += a.J.m0[c].y;
+                c11 += a.J.m1[c].y;
+                if (p >= 0) {
+                    c01 += a.J.wf0[p].y;
+                    c11 += a.J.wf1[p].y;
+                }
+            }
+            q.q01 = -c01 / c11;
+        } else {
+            q.q01 = -(d0.y / d1.y);
+        }
+        dec_pair(a.J.d0, a.J.d1, a.A.d0, a.A.d1, F32P(a.A32.d0), F32P(a.A32.d1), row, q, f32);
         d2 r = a.R[row];
         double b0 = -r.x, b1 = -r.y;
-        a.b[row] = mk2(b0 - f * b1, b1);
+        a.b[row] = mk2(q.q00 * b0 + q.q01 * b1, q.q10 * b0 + q.q11 * b1);
         if (!frac) {
-            dec_pair(a.J.m0, a.J.m1, a.A.m0, a.A.m1, F32P(a.A32.m0), F32P(a.A32.m1), pos, f, f32);
+            dec_pair(a.J.m0, a.J.m1, a.A.m0, a.A.m1, F32P(a.A32.m0), F32P(a.A32.m1), pos, q, f32);
         } else {
             for (int s = 0; s < 7; ++s)
                 dec_pair(a.J.f0, a.J.f1, a.A.f0, a.A.f1, F32P(a.A32.f0), F32P(a.A32.f1),
-                         (int64_t)s * n + pos, f, f32);
-            int p = a.fperf[pos];
+                         (int64_t)s * n + pos, q, f32);
             if (p >= 0)
-                dec_pair(a.J.fw0, a.J.fw1, a.A.fw0, a.A.fw1, F32P(a.A32.fw0), F32P(a.A32.fw1), p, f,
+                dec_pair(a.J.fw0, a.J.fw1, a.A.fw0, a.A.fw1, F32P(a.A32.fw0), F32P(a.A32.fw1), p, q,
                          f32);
         }
     } else {
         int w = b - bm - bf;
         int row = 2 * n + w;
+        const Q2 id{1.0, 0.0, 0.0, 1.0};
         if (threadIdx.x == 0) {
-            dec_pair(a.J.d0, a.J.d1, a.A.d0, a.A.d1, F32P(a.A32.d0), F32P(a.A32.d1), row, 0.0, f32);
+            dec_pair(a.J.d0, a.J.d1, a.A.d0, a.A.d1, F32P(a.A32.d0), F32P(a.A32.d1), row, id, f32);
             d2 r = a.R[row];
             a.b[row] = mk2(-r.x, -r.y);
         }
         for (int p = a.well_ptr[w] + threadIdx.x; p < a.well_ptr[w + 1]; p += blockDim.x)
-            dec_pair(a.J.wf0, a.J.wf1, a.A.wf0, a.A.wf1, F32P(a.A32.wf0), F32P(a.A32.wf1), p, 0.0, f32);
+            dec_pair(a.J.wf0, a.J.wf1, a.A.wf0, a.A.wf1, F32P(a.A32.wf0), F32P(a.A32.wf1), p, id, f32);
     }
 #undef F32P
 }
@@ -84,9 +131,13 @@ void launch_decouple(dp_sim* s) {
     a.A = s->A;
     a.A32 = s->A32;
     a.f32 = s->fp32;
+    a.variant = s->desc.decoupling;
     a.R = s->res;
     a.b = s->rhs;
-    a.fmask = nullptr;
+    a.fmask = t.fmask;
+    a.fcol = t.fcol;
+    a.fcell = t.fcell;
+    a.frow = t.frow;
     a.fperf = t.fperf;
     a.well_ptr = t.well_ptr;
     a.n = t.n;

@@ -78,6 +78,8 @@ def make_desc(model, precision=None, **opts):
     d.forcing_eta_min = float(opts.get("forcing_eta_min", 1e-8))
     d.forcing_eta_max = float(opts.get("forcing_eta_max", 0.9))
     d.precond_eager = int(opts.get("precond_eager", 0))
+    d.decoupling = {"gj": 0, "abf": 1, "ti": 2}[opts.get("decoupling", "gj")]
+    d.cpr_variant = {"fpf": 0, "fp": 1}[opts.get("cpr_variant", "fpf")]
     return d, keep
 
 
