@@ -33,7 +33,8 @@ def scaled_residual_norm(geo, R, dt, control):
     """max over rows of |R| scaled to a dimensionless size.
 
     Node rows: |R_a| dt / (rho_a,ref phi V) (a pore-volume fraction per step).
-    Rate rows: |R| / (rho_w,ref max(|Q|, 1e-6 m^3/s)).  BHP rows: |R| / target.
+    Rate rows: |R| / (rho_w,ref max(|Q|, 1e-6 m^3/s)); oil-rate rows the same
+    with rho_o,ref.  BHP rows: |R| / target.  (Reference porosity throughout.)
     """
     m = geo.m
     n = geo.n
@@ -45,6 +46,8 @@ def scaled_residual_norm(geo, R, dt, control):
         r = abs(R[4 * n + 2 * w])
         if control[w] == "rate":
             worst = max(worst, r / (m["rho_w_ref"] * max(abs(wl["target"]), 1e-6)))
+        elif control[w] == "orate":
+            worst = max(worst, r / (m["rho_o_ref"] * max(abs(wl["target"]), 1e-6)))
         else:
             target = wl["target"] if wl["control"] == "bhp" else wl["bhp_limit"]
             worst = max(worst, r / max(abs(target), 1.0))
@@ -77,7 +80,7 @@ def apply_update(geo, x, dx, control):
     s1 = np.where((s0 < hi) & (s1 > hi), hi, s1)
     y[1:4 * n:2] = np.clip(s1, 0.0, 1.0)
     for w, wl in enumerate(m["wells"]):
-        if control[w] != "rate":
+        if control[w] == "bhp":
             y[4 * n + 2 * w] = wl["target"] if wl["control"] == "bhp" else wl["bhp_limit"]
         y[4 * n + 2 * w + 1] = 0.0
     return y
@@ -201,12 +204,15 @@ def timestep(geo, x, dt, control, max_cuts=8, **newton_kw):
             xn, ok, its, info = newton_solve(geo, x, acc_old, h, control, **newton_kw)
             if not ok:
                 break
-            # BHP limit of rate injectors: switch once and redo
+            # BHP limits of rate-controlled wells (an injector's maximum, a
+            # producer's minimum): switch once and redo
             redo = False
             if not switched:
                 _, _, bhp = ph.unpack_state(xn, geo.n)
                 for w, wl in enumerate(geo.m["wells"]):
-                    if control[w] == "rate" and wl["kind"] == "inj" and bhp[w] > wl["bhp_limit"]:
+                    over = control[w] == "rate" and wl["kind"] == "inj" and bhp[w] > wl["bhp_limit"]
+                    under = control[w] == "orate" and wl["kind"] == "prod" and bhp[w] < wl["bhp_limit"]
+                    if over or under:
                         control[w] = "bhp"
                         redo = True
             if redo:

@@ -10,6 +10,7 @@ carries its bottom-hole pressure p_b and a dummy unknown (so that all blocks
 are 2x2); its first equation is the control equation (rate: the well's net
 mass rate, the sum of both phases' perforation rates, minus the target water
 mass rate, Eqs. (6)-(7) -- while every perforation injects, the water rate;
+oil rate (producers): the oil perforation rates plus the target oil mass rate;
 BHP: p_b minus the target) and its second is ``dummy = 0``.
 
 Global unknown index: node q -> (2q, 2q+1) = (p, S_w); well w -> (4n+2w,
@@ -124,7 +125,8 @@ def peaceman_re(dx, dy, kx, ky):
 def well_perforations(m):
     """For every well, the perforated cells and their well indices
     W = 2 pi k_h w_frac / (ln(r_e/r_w) + s) with k_h = sqrt(kx ky) dz and
-    w_frac = 1 (Eq. (8) with Eq. (10))."""
+    w_frac = 1 (Eq. (8) with Eq. (10)), or the well's own index ``wi`` when it
+    gives one (the examples of Sec. 4 state an injector's index directly)."""
     out = []
     nx, ny = m["nx"], m["ny"]
     for w in m["wells"]:
@@ -135,6 +137,8 @@ def well_perforations(m):
         re = peaceman_re(m["dx"], m["dy"], kx, ky)
         kh = np.sqrt(kx * ky) * m["dz"]
         wi = 2.0 * np.pi * kh / (np.log(re / w["rw"]) + w["skin"])
+        if w.get("wi", 0.0) > 0.0:
+            wi = np.full(cells.shape[0], float(w["wi"]))  # a well index given as data
         out.append((cells, wi))
     return out
 
@@ -176,6 +180,14 @@ def unpack_state(x, n):
     return x[0:4 * n:2], x[1:4 * n:2], x[4 * n::2]
 
 
+def porosity(geo, p):
+    """phi(p) = phi_ref (1 + c_r (p - p_ref)) per node, and d phi/dp (rock
+    compressibility; the examples of Sec. 4 give c_r, the benchmark models use
+    c_r = 0)."""
+    c_r = geo.m.get("c_r", 0.0)
+    return geo.phi * (1.0 + c_r * (p - geo.m["p_ref"])), geo.phi * c_r
+
+
 def initial_state(m):
     bhp = np.array([w["target"] if w["control"] == "bhp" else m["p0"].mean()
                     for w in m["wells"]], dtype=np.float64)
@@ -183,13 +195,13 @@ def initial_state(m):
 
 
 def accumulation(geo, x):
-    """Phase masses per node: M_o = V phi (1 - S_w) rho_o, M_w = V phi S_w rho_w
-    (porosity as a fraction of the cell bulk volume, no rock compressibility)."""
+    """Phase masses per node: M_o = V phi(p) (1 - S_w) rho_o, M_w = V phi(p) S_w
+    rho_w (porosity as a fraction of the cell bulk volume)."""
     m = geo.m
     p, sw, _ = unpack_state(x, geo.n)
     rho_o, _ = density(p, m["rho_o_ref"], m["c_o"], m["p_ref"])
     rho_w, _ = density(p, m["rho_w_ref"], m["c_w"], m["p_ref"])
-    vphi = geo.vol * geo.phi
+    vphi = geo.vol * porosity(geo, p)[0]
     return vphi * (1.0 - sw) * rho_o, vphi * sw * rho_w
 
 
@@ -249,7 +261,7 @@ def residual(geo, x, acc_old, dt, control):
     q_a,mf   = omega (k_ra rho_a/mu_a)_up (p_f - p_m), flowing fracture ->
                matrix; upstream = f if p_f >= p_m else m.
 
-    ``control[w]`` is 'rate' or 'bhp' for each well.
+    ``control[w]`` is 'rate', 'orate' or 'bhp' for each well.
     """
     m = geo.m
     n = geo.n
@@ -284,6 +296,8 @@ def residual(geo, x, acc_old, dt, control):
         wl = m["wells"][w]
         if control[w] == "rate":
             R[4 * n + 2 * w] = np.sum(qo + qw) - m["rho_w_ref"] * wl["target"]
+        elif control[w] == "orate":
+            R[4 * n + 2 * w] = np.sum(qo) + m["rho_o_ref"] * wl["target"]
         else:
             target = wl["target"] if wl["control"] == "bhp" else wl["bhp_limit"]
             R[4 * n + 2 * w] = bhp[w] - target
@@ -308,13 +322,15 @@ def jacobian(geo, x, dt, control):
 
     pr = _phase_props(m, p, sw)
     nodes = np.arange(2 * n)
-    vphi = geo.vol * geo.phi
+    phi, dphi_dp = porosity(geo, p)
+    vphi = geo.vol * phi
+    vdphi = geo.vol * dphi_dp
     rho_o, drho_o = pr["o"][0], pr["o"][1]
     rho_w, drho_w = pr["w"][0], pr["w"][1]
     # accumulation
-    add(2 * nodes, 2 * nodes, vphi * (1.0 - sw) * drho_o / dt)
+    add(2 * nodes, 2 * nodes, (1.0 - sw) * (vphi * drho_o + vdphi * rho_o) / dt)
     add(2 * nodes, 2 * nodes + 1, -vphi * rho_o / dt)
-    add(2 * nodes + 1, 2 * nodes, vphi * sw * drho_w / dt)
+    add(2 * nodes + 1, 2 * nodes, sw * (vphi * drho_w + vdphi * rho_w) / dt)
     add(2 * nodes + 1, 2 * nodes + 1, vphi * rho_w / dt)
     g = m["gravity"]
     fc, fd = 2 * geo.fc, 2 * geo.fd
@@ -383,11 +399,11 @@ def jacobian(geo, x, dt, control):
             add(2 * node + eq, 2 * node, -dq_dp)
             add(2 * node + eq, 2 * node + 1, -dq_ds)
             add(2 * node + eq, rw_idx, -dq_db)
-            if control[w] == "rate":
+            if control[w] == "rate" or (control[w] == "orate" and eq == 0):
                 add(rw_idx, 2 * node, dq_dp)
                 add(rw_idx, 2 * node + 1, dq_ds)
                 add(rw_idx, rw_idx, np.sum(dq_db))
-        if control[w] != "rate":
+        if control[w] == "bhp":
             add(rw_idx, rw_idx, 1.0)
         add(rw_idx + 1, rw_idx + 1, 1.0)
     r = np.concatenate(rows)

@@ -23,3 +23,4 @@ from .models import (  # noqa: F401
     model_tiny,
     random_state,
 )
+from .examples import paper_example  # noqa: F401
