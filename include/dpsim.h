@@ -53,7 +53,7 @@ enum {
 };
 
 enum { DP_WELL_INJ = 0, DP_WELL_PROD = 1 };   /* water injector | producer */
-enum { DP_CTRL_RATE = 0, DP_CTRL_BHP = 1 };   /* control equation of a well */
+enum { DP_CTRL_RATE = 0, DP_CTRL_BHP = 1, DP_CTRL_ORATE = 2 };   /* control equation of a well */
 enum { DP_FP64 = 0, DP_FP32 = 1 };            /* preconditioner precision */
 /* Decoupling D^-1 of Eq. (14), per node row (Sec. 3.2): DP_DEC_GJ one
  * Gauss-Jordan step on the diagonal block (row0 -= a01/a11 row1; for 2x2 blocks
@@ -72,19 +72,26 @@ typedef struct dp_sim dp_sim;
 /* A vertical well perforating the fracture nodes of cells (i, j, k0..k1).
  * Eq. (6): perforation rate q = rho W lambda (p_b - p); Eq. (7): well rate is
  * the sum over perforations; Eq. (8) with Eq. (10): W = 2 pi sqrt(kx ky) dz /
- * (ln(r_e/r_w) + skin), r_e Peaceman's.  Mobility is taken upstream: an
+ * (ln(r_e/r_w) + skin), r_e Peaceman's, unless wi > 0 gives W directly (the
+ * examples of Sec. 4 state an injector's index).  Mobility is taken upstream: an
  * injector's perforation with p_b >= p injects water only, with the block's
  * total mobility; a perforation in back-flow produces each phase with the
- * block's phase mobility.  Rate control fixes the well's net mass rate (both
- * phases) at rho_w_ref * target.  A rate-controlled injector whose converged p_b
- * exceeds bhp_limit switches to BHP control at bhp_limit (once per step). */
+ * block's phase mobility.  Rate control (injectors) fixes the well's net mass
+ * rate (both phases) at rho_w_ref * target; oil-rate control (producers) fixes
+ * the produced oil mass rate at rho_o_ref * target.  A rate-controlled injector
+ * whose converged p_b exceeds bhp_limit (its maximum), or an oil-rate producer
+ * whose converged p_b falls below bhp_limit (its minimum), switches to BHP
+ * control at bhp_limit (once per step). */
 typedef struct {
     int32_t i, j, k0, k1;
     int32_t kind;     /* DP_WELL_INJ | DP_WELL_PROD */
-    int32_t control;  /* DP_CTRL_RATE (injectors only) | DP_CTRL_BHP */
-    double target;    /* rate: m^3/s at rho_w_ref; BHP: Pa */
-    double bhp_limit; /* Pa */
+    int32_t control;  /* DP_CTRL_RATE (injectors) | DP_CTRL_ORATE (producers) | DP_CTRL_BHP */
+    double target;    /* rate: m^3/s at rho_w_ref; oil rate: m^3/s at rho_o_ref, > 0
+                         for production; BHP: Pa */
+    double bhp_limit; /* Pa: an injector's maximum, a producer's minimum */
     double rw, skin;  /* m, - */
+    double wi;        /* well index W, m^3, used for every perforation when > 0;
+                         0 computes Peaceman's */
 } dp_well;
 
 typedef struct {
@@ -97,6 +104,8 @@ typedef struct {
     const double *phi_f, *phi_m; /* [n] */
     double sigma;             /* shape factor, 1/m^2: omega = sigma km V */
     double rho_w_ref, rho_o_ref, p_ref, c_w, c_o; /* rho = rho_ref exp(c (p - p_ref)) */
+    double c_r;               /* rock compressibility, 1/Pa: the pore volume of a node is
+                                 V phi (1 + c_r (p - p_ref)) (Sec. 4 examples); 0 for none */
     double mu_w, mu_o;        /* Pa s */
     double swc, sor, n_w, n_o, krw_max, kro_max; /* Corey curves */
     int32_t nwells;
@@ -162,7 +171,7 @@ typedef struct {
 dp_status sim_footprint(const dp_sim_desc *desc, size_t *device_bytes);
 
 /* Create a handle.  p0, sw0: [2n] initial node states in canonical order
- * (host).  Rate-injector p_b starts at the mean of p0; BHP wells at their
+ * (host).  Rate and oil-rate wells start with p_b at the mean of p0; BHP wells at their
  * target.  d_workspace: device memory of at least sim_footprint bytes.
  * hip_stream: a hipStream_t (NULL = default stream). */
 dp_status sim_create(const dp_sim_desc *desc, const double *p0, const double *sw0,

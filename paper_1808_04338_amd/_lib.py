@@ -20,7 +20,7 @@ STATUS_NAMES = {0: "DP_OK", -1: "DP_E_INVALID", -2: "DP_E_NOMEM", -3: "DP_E_DEVI
                 -4: "DP_E_NOCONV", -5: "DP_E_STATE", -6: "DP_E_NUMERIC"}
 
 DP_WELL_INJ, DP_WELL_PROD = 0, 1
-DP_CTRL_RATE, DP_CTRL_BHP = 0, 1
+DP_CTRL_RATE, DP_CTRL_BHP, DP_CTRL_ORATE = 0, 1, 2
 DP_FP64, DP_FP32 = 0, 1
 
 _dptr = C.POINTER(C.c_double)
@@ -32,7 +32,7 @@ class DpWell(C.Structure):
     _fields_ = [("i", C.c_int32), ("j", C.c_int32), ("k0", C.c_int32), ("k1", C.c_int32),
                 ("kind", C.c_int32), ("control", C.c_int32),
                 ("target", C.c_double), ("bhp_limit", C.c_double),
-                ("rw", C.c_double), ("skin", C.c_double)]
+                ("rw", C.c_double), ("skin", C.c_double), ("wi", C.c_double)]
 
 
 class DpSimDesc(C.Structure):
@@ -43,7 +43,7 @@ class DpSimDesc(C.Structure):
                 ("phi_f", _dptr), ("phi_m", _dptr),
                 ("sigma", C.c_double),
                 ("rho_w_ref", C.c_double), ("rho_o_ref", C.c_double), ("p_ref", C.c_double),
-                ("c_w", C.c_double), ("c_o", C.c_double),
+                ("c_w", C.c_double), ("c_o", C.c_double), ("c_r", C.c_double),
                 ("mu_w", C.c_double), ("mu_o", C.c_double),
                 ("swc", C.c_double), ("sor", C.c_double), ("n_w", C.c_double), ("n_o", C.c_double),
                 ("krw_max", C.c_double), ("kro_max", C.c_double),

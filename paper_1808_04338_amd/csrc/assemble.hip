@@ -47,13 +47,19 @@ __global__ void geometry_kernel(GeoIn g, const int* __restrict__ fcol, const int
     depth[c] = g.top_depth + k * g.dz;
 }
 
-// Peaceman well index of every perforation: W = 2 pi sqrt(kx ky) dz / (ln(r_e/r_w) + s).
+// Peaceman well index of every perforation: W = 2 pi sqrt(kx ky) dz / (ln(r_e/r_w) + s),
+// or the well's own index where it gives one (perf_wi > 0).
 __global__ void well_index_kernel(const double* __restrict__ kx, const double* __restrict__ ky,
                                   const int* __restrict__ perf_cell, const double* __restrict__ perf_rw,
-                                  const double* __restrict__ perf_skin, int nperf, double dx,
+                                  const double* __restrict__ perf_skin,
+                                  const double* __restrict__ perf_wi, int nperf, double dx,
                                   double dy, double dz, double* wi) {
     int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= nperf) return;
+    if (perf_wi[p] > 0.0) {
+        wi[p] = perf_wi[p];
+        return;
+    }
     int c = perf_cell[p];
     double ryx = sqrt(ky[c] / kx[c]);
     double rxy = sqrt(kx[c] / ky[c]);
@@ -66,7 +72,8 @@ __global__ void well_index_kernel(const double* __restrict__ kx, const double* _
 
 void launch_geometry(dp_sim* s, const double* kx, const double* ky, const double* kz,
                      const double* km, const double* phi_f, const double* phi_m,
-                     const int* perf_cell, const double* perf_rw, const double* perf_skin) {
+                     const int* perf_cell, const double* perf_rw, const double* perf_skin,
+                     const double* perf_wi) {
     Topo& t = s->topo;
     GeoIn g{kx, ky, kz, km, phi_f, phi_m, s->desc.dx, s->desc.dy, s->desc.dz,
             s->desc.top_depth, s->desc.sigma, t.nx, t.ny, t.n};
@@ -75,7 +82,8 @@ void launch_geometry(dp_sim* s, const double* kx, const double* ky, const double
     DP_LAUNCH_CHECK();
     if (t.nperf > 0) {
         well_index_kernel<<<ceil_div(t.nperf, 256), 256, 0, s->stream>>>(
-            kx, ky, perf_cell, perf_rw, perf_skin, t.nperf, s->desc.dx, s->desc.dy, s->desc.dz, t.wi);
+            kx, ky, perf_cell, perf_rw, perf_skin, perf_wi, t.nperf, s->desc.dx, s->desc.dy, s->desc.dz,
+            t.wi);
         DP_LAUNCH_CHECK();
     }
 }
@@ -97,11 +105,12 @@ Phys make_phys(const dp_sim* s) {
     P.kro_max = s->kro_max;
     P.g = s->gravity;
     P.dz = s->dz;
+    P.c_r = s->c_r;
     return P;
 }
 
 // ---------------------------------------------------------------------------
-// Accumulation M = V phi (S rho) per node, at the start of a step
+// Accumulation M = V phi(p) (S rho) per node, at the start of a step
 // ---------------------------------------------------------------------------
 __global__ void accumulation_kernel(Phys P, const d2* __restrict__ x, const double* __restrict__ pvf,
                                     const double* __restrict__ pvm, const int* __restrict__ fcell,
@@ -112,7 +121,8 @@ __global__ void accumulation_kernel(Phys P, const d2* __restrict__ x, const doub
     d2 v = x[r];
     double rho_o = P.rho_ref[0] * exp(P.c[0] * (v.x - P.p_ref));
     double rho_w = P.rho_ref[1] * exp(P.c[1] * (v.x - P.p_ref));
-    acc[r] = mk2(pv * (1.0 - v.y) * rho_o, pv * v.y * rho_w);
+    double pvp = pv * (1.0 + P.c_r * (v.x - P.p_ref));
+    acc[r] = mk2(pvp * (1.0 - v.y) * rho_o, pvp * v.y * rho_w);
 }
 
 void launch_accumulation(dp_sim* s, const d2* x, d2* acc) {
@@ -150,17 +160,20 @@ struct AsmArgs {
     d2* R;
 };
 
-// Accumulation terms of one node row: residual (M - M^n)/dt and diagonal block.
+// Accumulation terms of one node row: residual (M - M^n)/dt and diagonal block,
+// pv = V phi_ref and the pore volume V phi(p) = pv (1 + c_r (p - p_ref)).
 __device__ inline void accum_row(const Phys& P, double pv, double dt, double p, double s,
                                  const Props& pr, d2 old, double R[2], double D[2][2]) {
-    double mo = pv * (1.0 - s) * pr.rho[0];
-    double mw = pv * s * pr.rho[1];
+    double pvp = pv * (1.0 + P.c_r * (p - P.p_ref));
+    double dpv = pv * P.c_r;
+    double mo = pvp * (1.0 - s) * pr.rho[0];
+    double mw = pvp * s * pr.rho[1];
     R[0] = (mo - old.x) / dt;
     R[1] = (mw - old.y) / dt;
-    D[0][0] = pv * (1.0 - s) * pr.drho[0] / dt;
-    D[0][1] = -pv * pr.rho[0] / dt;
-    D[1][0] = pv * s * pr.drho[1] / dt;
-    D[1][1] = pv * pr.rho[1] / dt;
+    D[0][0] = (1.0 - s) * (pvp * pr.drho[0] + dpv * pr.rho[0]) / dt;
+    D[0][1] = -pvp * pr.rho[0] / dt;
+    D[1][0] = s * (pvp * pr.drho[1] + dpv * pr.rho[1]) / dt;
+    D[1][1] = pvp * pr.rho[1] / dt;
 }
 
 // Matrix row of cell c: accumulation minus the transfer from its fracture node.
@@ -271,14 +284,16 @@ __device__ void assemble_fracture_row(const AsmArgs& a, int q) {
 }
 
 // Well row w (one block): rate control sum_p (q_o,p + q_w,p) - rho_w,ref Q = 0
-// (the net mass rate; the water rate while every perforation injects), or BHP
+// (the net mass rate; the water rate while every perforation injects), oil-rate
+// control sum_p q_o,p + rho_o,ref Q = 0 (a producer's oil mass rate), or BHP
 // control p_b - target = 0; second row: dummy = 0.  The perforation sum is
 // reduced in a fixed order.
 __device__ void assemble_well_row(const AsmArgs& a, int w) {
     __shared__ double sh_q[256 / WAVE], sh_db[256 / WAVE];
     const Phys& P = a.P;
     int n = a.n;
-    int rate = a.well_ctrl[w] == DP_CTRL_RATE;
+    const int ctrl = a.well_ctrl[w];
+    const bool rate = ctrl == DP_CTRL_RATE, orate = ctrl == DP_CTRL_ORATE;
     d2 xw = a.x[2 * n + w];
     double q = 0.0, db = 0.0;
     for (int p = a.well_ptr[w] + threadIdx.x; p < a.well_ptr[w + 1]; p += blockDim.x) {
@@ -286,9 +301,13 @@ __device__ void assemble_well_row(const AsmArgs& a, int w) {
         d2 xf = a.x[pos];
         Props pf = props(P, xf.x, xf.y);
         Perf r = perf_rate(P, a.well_kind[w], a.wi[p], xw.x, xf.x, pf);
-        q += r.q[0] + r.q[1];
-        db += r.db[0] + r.db[1];
-        if (rate) {
+        if (orate) {
+            q += r.q[0];
+            db += r.db[0];
+            a.J.wf0[p] = mk2(r.dp[0], r.ds[0]);
+        } else if (rate) {
+            q += r.q[0] + r.q[1];
+            db += r.db[0] + r.db[1];
             a.J.wf0[p] = mk2(r.dp[0] + r.dp[1], r.ds[0] + r.ds[1]);
         } else {
             a.J.wf0[p] = mk2(0.0, 0.0);
@@ -313,6 +332,9 @@ __device__ void assemble_well_row(const AsmArgs& a, int w) {
         double r0, d00;
         if (rate) {
             r0 = qs - P.rho_ref[1] * a.well_target[w];
+            d00 = dbs;
+        } else if (orate) {
+            r0 = qs + P.rho_ref[0] * a.well_target[w];
             d00 = dbs;
         } else {
             r0 = xw.x - a.well_target[w];
@@ -494,7 +516,7 @@ __global__ void newton_update_kernel(d2* x, const d2* __restrict__ dx, int n, in
         x[r] = mk2(v.x + d.x, s);
     } else if (r < 2 * n + nw) {
         int w = r - 2 * n;
-        double pb = well_ctrl[w] == DP_CTRL_RATE ? x[r].x + dx[r].x : well_target[w];
+        double pb = well_ctrl[w] == DP_CTRL_BHP ? well_target[w] : x[r].x + dx[r].x;
         x[r] = mk2(pb, 0.0);
     }
 }

@@ -11,7 +11,8 @@ Phys make_phys(const dp_sim* s);
 // assemble.hip
 void launch_geometry(dp_sim* s, const double* kx, const double* ky, const double* kz,
                      const double* km, const double* phi_f, const double* phi_m,
-                     const int* perf_cell, const double* perf_rw, const double* perf_skin);
+                     const int* perf_cell, const double* perf_rw, const double* perf_skin,
+                     const double* perf_wi);
 void launch_accumulation(dp_sim* s, const d2* x, d2* acc);
 void launch_assemble(dp_sim* s, double dt);
 struct ResNorm {

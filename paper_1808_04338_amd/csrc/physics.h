@@ -9,6 +9,7 @@ namespace dp {
 struct Phys {
     double rho_ref[2], c[2], mu[2];
     double p_ref, swc, sor, n_w, n_o, krw_max, kro_max, g, dz;
+    double c_r;  // rock compressibility: phi(p) = phi_ref (1 + c_r (p - p_ref))
 };
 
 // Per-node properties: densities rho = rho_ref exp(c (p - p_ref)), Corey relative

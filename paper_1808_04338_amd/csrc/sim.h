@@ -159,7 +159,7 @@ struct dp_sim {
     dp::Topo topo;
 
     // physics constants (copied from the descriptor)
-    double rho_w_ref, rho_o_ref, p_ref, c_w, c_o, mu_w, mu_o;
+    double rho_w_ref, rho_o_ref, p_ref, c_w, c_o, c_r, mu_w, mu_o;
     double swc, sor, n_w, n_o, krw_max, kro_max, gravity, dz;
     double pore_volume = 0.0;  // sum over nodes of V phi (material-balance scale)
 

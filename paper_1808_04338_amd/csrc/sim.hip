@@ -62,10 +62,14 @@ static void validate(const dp_sim_desc& d) {
             wl.k0 > wl.k1)
             fail(DP_E_INVALID, "well " + std::to_string(w) + " outside the grid");
         if (wl.kind != DP_WELL_INJ && wl.kind != DP_WELL_PROD) fail(DP_E_INVALID, "bad well kind");
-        if (wl.control != DP_CTRL_RATE && wl.control != DP_CTRL_BHP) fail(DP_E_INVALID, "bad well control");
+        if (wl.control != DP_CTRL_RATE && wl.control != DP_CTRL_BHP && wl.control != DP_CTRL_ORATE)
+            fail(DP_E_INVALID, "bad well control");
         if (wl.kind == DP_WELL_PROD && wl.control == DP_CTRL_RATE)
             fail(DP_E_INVALID, "rate control is supported for injectors only");
+        if (wl.kind == DP_WELL_INJ && wl.control == DP_CTRL_ORATE)
+            fail(DP_E_INVALID, "oil-rate control is supported for producers only");
         if (!(wl.rw > 0)) fail(DP_E_INVALID, "well radius must be positive");
+        if (!(wl.wi >= 0) || !std::isfinite(wl.wi)) fail(DP_E_INVALID, "well index must be >= 0 and finite");
     }
 }
 
@@ -75,7 +79,7 @@ struct HostTopo {
     int n, nw, nb, nred, nperf;
     std::vector<int> fcell, frow, fcol, fperf, perf_q, perf_well, perf_cell, well_ptr;
     std::vector<unsigned char> fmask;
-    std::vector<double> perf_rw, perf_skin;
+    std::vector<double> perf_rw, perf_skin, perf_wi;
     std::vector<int> ap_rowptr, ap_col, ap_src;
     int64_t nfaces2 = 0;  // sum over fracture rows of present slots
 };
@@ -135,6 +139,7 @@ static void build_topology(const dp_sim_desc& d, HostTopo& h) {
             h.perf_cell.push_back(c);
             h.perf_rw.push_back(wl.rw);
             h.perf_skin.push_back(wl.skin);
+            h.perf_wi.push_back(wl.wi);
         }
         h.well_ptr[w + 1] = (int)h.perf_q.size();
     }
@@ -277,6 +282,7 @@ static void make_phys_scalars(dp_sim* s) {
     s->p_ref = d.p_ref;
     s->c_w = d.c_w;
     s->c_o = d.c_o;
+    s->c_r = d.c_r;
     s->mu_w = d.mu_w;
     s->mu_o = d.mu_o;
     s->swc = d.swc;
@@ -313,6 +319,9 @@ static void set_controls(dp_sim* s, const std::vector<int>& ctrl) {
         if (ctrl[w] == DP_CTRL_RATE) {
             target[w] = wl.target;
             scale[w] = 1.0 / (s->rho_w_ref * std::max(std::fabs(wl.target), 1e-6));
+        } else if (ctrl[w] == DP_CTRL_ORATE) {
+            target[w] = wl.target;
+            scale[w] = 1.0 / (s->rho_o_ref * std::max(std::fabs(wl.target), 1e-6));
         } else {
             target[w] = wl.control == DP_CTRL_BHP ? wl.target : wl.bhp_limit;
             scale[w] = 1.0 / std::max(std::fabs(target[w]), 1.0);
@@ -501,8 +510,9 @@ __global__ void mass_sums_kernel(Phys P, const d2* __restrict__ x, const d2* __r
         d2 xx = x[r];
         double rho_o = P.rho_ref[0] * exp(P.c[0] * (xx.x - P.p_ref));
         double rho_w = P.rho_ref[1] * exp(P.c[1] * (xx.x - P.p_ref));
-        v[2] += pv * (1.0 - xx.y) * rho_o;
-        v[3] += pv * xx.y * rho_w;
+        double pvp = pv * (1.0 + P.c_r * (xx.x - P.p_ref));
+        v[2] += pvp * (1.0 - xx.y) * rho_o;
+        v[3] += pvp * xx.y * rho_w;
     }
     for (int p = threadIdx.x; p < nperf; p += blockDim.x) {
         int pos = n + perf_q[p];
@@ -678,12 +688,15 @@ static int do_timestep(dp_sim* s, double dt, dp_step_info* info) {
             ok = newton_loop(s, h, &out.newton_iters, &out.lin_iters, &res);
             out.res_scaled = res;
             if (!ok || switched) break;
-            // a rate injector above its BHP limit switches to BHP control at the limit
+            // a rate injector above its BHP maximum, or an oil-rate producer below its
+            // BHP minimum, switches to BHP control at that limit
             std::vector<d2> xw = dl(s, s->x + 2 * s->topo.n, s->topo.nw);
             bool redo = false;
             for (int w = 0; w < s->topo.nw; ++w) {
                 const dp_well& wl = s->wells[w];
-                if (ctrl[w] == DP_CTRL_RATE && wl.kind == DP_WELL_INJ && xw[w].x > wl.bhp_limit) {
+                bool over = ctrl[w] == DP_CTRL_RATE && wl.kind == DP_WELL_INJ && xw[w].x > wl.bhp_limit;
+                bool under = ctrl[w] == DP_CTRL_ORATE && wl.kind == DP_WELL_PROD && xw[w].x < wl.bhp_limit;
+                if (over || under) {
                     ctrl[w] = DP_CTRL_BHP;
                     redo = true;
                 }
@@ -894,10 +907,12 @@ dp_status sim_create(const dp_sim_desc* desc, const double* p0, const double* sw
         int* pc = sc.get<int>(h.nperf, "perforations");
         double* prw = sc.get<double>(h.nperf, "perforations");
         double* psk = sc.get<double>(h.nperf, "perforations");
+        double* pwi = sc.get<double>(h.nperf, "perforations");
         up(pc, h.perf_cell.data(), sizeof(int) * h.nperf);
         up(prw, h.perf_rw.data(), sizeof(double) * h.nperf);
         up(psk, h.perf_skin.data(), sizeof(double) * h.nperf);
-        launch_geometry(s, dk[0], dk[1], dk[2], dk[3], dk[4], dk[5], pc, prw, psk);
+        up(pwi, h.perf_wi.data(), sizeof(double) * h.nperf);
+        launch_geometry(s, dk[0], dk[1], dk[2], dk[3], dk[4], dk[5], pc, prw, psk, pwi);
         {
             double vol = desc->dx * desc->dy * desc->dz, pv = 0.0;
             for (int c = 0; c < n; ++c) pv += vol * desc->phi_f[c] + vol * desc->phi_m[c];

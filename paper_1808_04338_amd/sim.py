@@ -12,6 +12,7 @@ import scipy.sparse as sp
 from . import _lib as L
 
 _PREC = {"fp64": L.DP_FP64, "fp32": L.DP_FP32}
+_CTRL = {"rate": L.DP_CTRL_RATE, "bhp": L.DP_CTRL_BHP, "orate": L.DP_CTRL_ORATE}
 
 
 def _dp(a):
@@ -46,15 +47,17 @@ def make_desc(model, precision=None, **opts):
     for k in ("sigma", "rho_w_ref", "rho_o_ref", "p_ref", "c_w", "c_o", "mu_w", "mu_o",
               "swc", "sor", "n_w", "n_o", "krw_max", "kro_max"):
         setattr(d, k, float(model[k]))
+    d.c_r = float(model.get("c_r", 0.0))
     wells = (L.DpWell * max(len(model["wells"]), 1))()
     for w, wl in enumerate(model["wells"]):
         wells[w].i, wells[w].j, wells[w].k0, wells[w].k1 = wl["i"], wl["j"], wl["k0"], wl["k1"]
         wells[w].kind = L.DP_WELL_INJ if wl["kind"] == "inj" else L.DP_WELL_PROD
-        wells[w].control = L.DP_CTRL_RATE if wl["control"] == "rate" else L.DP_CTRL_BHP
+        wells[w].control = _CTRL[wl["control"]]
         wells[w].target = wl["target"]
         wells[w].bhp_limit = wl["bhp_limit"]
         wells[w].rw = wl["rw"]
         wells[w].skin = wl["skin"]
+        wells[w].wi = float(wl.get("wi", 0.0))
     keep.append(wells)
     d.nwells = len(model["wells"])
     d.wells = wells
