@@ -227,6 +227,46 @@ def precond_study(nz, steps, rtol):
     return out
 
 
+def example_run(number, grid, days, forcing, precision):
+    """A whole run of the paper's Example 1 or 2 (Sec. 4) over its printed
+    period, optionally on a larger grid with the same cells (the paper's Example 3
+    is Example 1 on 500x500x50).  Every timestep prints one progress line."""
+    import torch
+
+    import synth
+    from paper_1808_04338_amd import Sim
+
+    t0 = time.perf_counter()
+    model = synth.paper_example(number, grid=grid, days=days)
+    log("example %d on %dx%dx%d: model built in %.1f s" % (number, model["nx"], model["ny"], model["nz"],
+                                                           time.perf_counter() - t0))
+    sim = Sim(model, precision=precision, forcing=forcing)
+    log("handle created: %d DOF, %.1f GB of device memory" % (sim.n_dof, sim.footprint / 1e9))
+    torch.cuda.synchronize()
+    newton = lin = cuts = substeps = 0
+    t_day = 0.0
+    t0 = time.perf_counter()
+    for k, dt in enumerate(model["schedule"]):
+        a = time.perf_counter()
+        info = sim.timestep(dt)
+        newton += info["newton_iters"]
+        lin += info["lin_iters"]
+        cuts += info["cuts"]
+        substeps += info["substeps"]
+        t_day += dt / 86400.0
+        log("step %d/%d t=%.0f d: %d Newton, %d linear, %d cuts, %.2f s" % (
+            k + 1, len(model["schedule"]), t_day, info["newton_iters"], info["lin_iters"], info["cuts"],
+            time.perf_counter() - a))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    out = dict(example=number, grid=[model["nx"], model["ny"], model["nz"]], dof=sim.n_dof,
+               days=t_day, timesteps=len(model["schedule"]), substeps=substeps, cuts=cuts,
+               newton_iters=newton, linear_iters=lin, wall_s=wall, footprint_gb=sim.footprint / 1e9,
+               precision=precision, forcing=forcing)
+    sim.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -253,6 +293,13 @@ def main():
     ap.add_argument("--precond-study", type=int, default=0,
                     help="instead of the benchmark: that many timed solves with each decoupling and "
                          "CPR composition")
+    ap.add_argument("--example", type=int, default=0,
+                    help="instead of the benchmark: a whole run of the paper's Example 1 or 2")
+    ap.add_argument("--grid", type=int, nargs=3, default=None,
+                    help="with --example: grid dimensions (same cells as printed)")
+    ap.add_argument("--days", type=float, default=None, help="with --example: simulated period")
+    ap.add_argument("--forcing", type=int, default=0, help="with --example: forcing choice of Eq. (13)")
+    ap.add_argument("--precision", default="fp32", help="with --example: preconditioner precision")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -267,6 +314,12 @@ def main():
                           "workload": "dual-porosity oil-water 60x60x10 layered five-spot, 144,010 DOF, "
                                       "5-day steps, FP32 preconditioner",
                           "data": "synthetic", "results": rec}))
+        return
+    if args.example > 0:
+        rec = example_run(args.example, tuple(args.grid) if args.grid else None, args.days, args.forcing,
+                          args.precision)
+        print(json.dumps({"study": "whole run of the paper's Example %d (Sec. 4)" % args.example,
+                          "data": "synthetic (printed inputs, stated readings)", "results": rec}))
         return
     if args.precond_study > 0:
         rec = precond_study(args.nz, args.precond_study, args.rtol)

@@ -166,6 +166,7 @@ struct dp_sim {
     // state, [nb] in elimination order: x = (p, S_w) per node, (p_b, dummy) per well
     dp::d2* x = nullptr;
     dp::d2* x_save = nullptr;   // state at the start of the step (rollback)
+    dp::d2* x_sub = nullptr;    // state at the start of the current sub-step (retries)
     dp::d2* acc_old = nullptr;  // [2n nodes] (M_o^n, M_w^n)
     dp::d2* res = nullptr;      // R
     dp::d2* rhs = nullptr;      // decoupled right-hand side -D^-1 R

@@ -225,6 +225,7 @@ static Layout layout(dp_sim* s, Arena& a, const HostTopo& h) {
     t.wi = a.get<double>(nperf, "geometry");
     s->x = a.get<d2>(nb, "state");
     s->x_save = a.get<d2>(nb, "state");
+    s->x_sub = a.get<d2>(nb, "state");
     s->acc_old = a.get<d2>(2 * (int64_t)n, "state");
     s->res = a.get<d2>(nb, "residual");
     s->rhs = a.get<d2>(nb, "rhs");
@@ -493,16 +494,21 @@ static int gmres(dp_sim* s, double rtol, int maxit, int* iters, double* rel_res)
 }
 
 // ---------------------------------------------------------------------------
-// Mass balance sums: [M_o^n, M_w^n, M_o, M_w, Q_o, Q_w]
+// Mass balance sums: [M_o^n, M_w^n, M_o, M_w, Q_o, Q_w].  Block partials over a
+// fixed grid (grid-stride, fixed order), then one block adds them in block
+// order in a second kernel, so the sums do not depend on timing.
 // ---------------------------------------------------------------------------
+constexpr int MS_BLOCKS = 512;
+
 __global__ void mass_sums_kernel(Phys P, const d2* __restrict__ x, const d2* __restrict__ acc_old,
                                  const double* __restrict__ pvf, const double* __restrict__ pvm,
                                  const int* __restrict__ fcell, const int* __restrict__ perf_q,
                                  const int* __restrict__ perf_well, const int* __restrict__ well_kind,
-                                 const double* __restrict__ wi, int n, int nperf, double* out) {
+                                 const double* __restrict__ wi, int n, int nperf, double* part) {
     __shared__ double sh[6][256 / WAVE];
     double v[6] = {0, 0, 0, 0, 0, 0};
-    for (int r = threadIdx.x; r < 2 * n; r += blockDim.x) {
+    const int stride = gridDim.x * blockDim.x;
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < 2 * n; r += stride) {
         d2 o = acc_old[r];
         v[0] += o.x;
         v[1] += o.y;
@@ -514,7 +520,7 @@ __global__ void mass_sums_kernel(Phys P, const d2* __restrict__ x, const d2* __r
         v[2] += pvp * (1.0 - xx.y) * rho_o;
         v[3] += pvp * xx.y * rho_w;
     }
-    for (int p = threadIdx.x; p < nperf; p += blockDim.x) {
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < nperf; p += stride) {
         int pos = n + perf_q[p];
         d2 xf = x[pos];
         Props pr = props(P, xf.x, xf.y);
@@ -531,15 +537,27 @@ __global__ void mass_sums_kernel(Phys P, const d2* __restrict__ x, const d2* __r
     if (threadIdx.x < 6) {
         double t = 0;
         for (int i = 0; i < (int)(blockDim.x / WAVE); ++i) t += sh[threadIdx.x][i];
+        part[6 * (int64_t)blockIdx.x + threadIdx.x] = t;
+    }
+}
+
+__global__ void mass_sums_final(const double* __restrict__ part, int nblk, double* out) {
+    // six lanes of the first wave each add one quantity over the blocks in order
+    if (threadIdx.x < 6) {
+        double t = 0;
+        for (int b = 0; b < nblk; ++b) t += part[6 * (int64_t)b + threadIdx.x];
         out[threadIdx.x] = t;
     }
 }
 
 static void mass_sums(dp_sim* s, double out[6]) {
     Topo& t = s->topo;
-    mass_sums_kernel<<<1, 256, 0, s->stream>>>(make_phys(s), s->x, s->acc_old, t.pvf, t.pvm, t.fcell,
-                                               t.perf_q, t.perf_well, t.well_kind, t.wi, t.n, t.nperf,
-                                               s->red_out + 128);
+    int nblk = (int)std::min<int64_t>(MS_BLOCKS, std::max<int64_t>(1, ceil_div(2 * (int64_t)t.n, 256)));
+    mass_sums_kernel<<<nblk, 256, 0, s->stream>>>(make_phys(s), s->x, s->acc_old, t.pvf, t.pvm, t.fcell,
+                                                  t.perf_q, t.perf_well, t.well_kind, t.wi, t.n, t.nperf,
+                                                  s->red_part);
+    DP_LAUNCH_CHECK();
+    mass_sums_final<<<1, 64, 0, s->stream>>>(s->red_part, nblk, s->red_out + 128);
     DP_LAUNCH_CHECK();
     DP_HIP(hipMemcpyAsync(out, s->red_out + 128, sizeof(double) * 6, hipMemcpyDeviceToHost, s->stream));
     DP_HIP(hipStreamSynchronize(s->stream));
@@ -675,8 +693,8 @@ static int do_timestep(dp_sim* s, double dt, dp_step_info* info) {
     std::vector<int> ctrl0 = host_ctrl(s);
     std::vector<int> ctrl = ctrl0;
     copy_state(s, s->x, s->x_save);
-    // state at the start of the current sub-step (host copy, for retries)
-    std::vector<d2> hsub = dl(s, s->x, s->topo.nb);
+    // state at the start of the current sub-step (device copy, for retries)
+    copy_state(s, s->x, s->x_sub);
     double remaining = dt, h = dt;
     int cuts = 0;
     while (remaining > 0.0) {
@@ -704,11 +722,10 @@ static int do_timestep(dp_sim* s, double dt, dp_step_info* info) {
             if (!redo) break;
             switched = true;
             set_controls(s, ctrl);
-            DP_HIP(hipMemcpyAsync(s->x, hsub.data(), sizeof(d2) * hsub.size(), hipMemcpyHostToDevice,
-                                  s->stream));
+            copy_state(s, s->x_sub, s->x);
         }
         if (!ok) {
-            DP_HIP(hipMemcpyAsync(s->x, hsub.data(), sizeof(d2) * hsub.size(), hipMemcpyHostToDevice, s->stream));
+            copy_state(s, s->x_sub, s->x);
             ++cuts;
             if (cuts > d.max_cuts) {
                 copy_state(s, s->x_save, s->x);
@@ -733,7 +750,7 @@ static int do_timestep(dp_sim* s, double dt, dp_step_info* info) {
         remaining -= h;
         out.dt += h;
         h *= 2.0;  // after an accepted sub-step the next may be twice as long
-        hsub = dl(s, s->x, s->topo.nb);
+        copy_state(s, s->x, s->x_sub);
     }
     out.cuts = cuts;
     if (info) *info = out;
