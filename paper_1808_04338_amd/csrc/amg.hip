@@ -814,10 +814,14 @@ static void build_op(dp_sim* s, const Csr& A, Op& op, bool pad_self, Arena& H, A
         }
     } else {
         op.kind = 1;
+        // two entries per lane and pass, at least 4 lanes per row (measured best
+        // over 1-4 entries and 1-4 lanes on the V-cycle of the 4.49M-DOF model)
         double mean = A.n > 0 ? (double)A.nnz / A.n : 1.0;
+        const int U = 2;
         int G = 4;
-        while (G < 64 && G < mean) G <<= 1;
+        while (G < 64 && G * U < mean) G <<= 1;
         op.G = G;
+        op.U = U;
         op.rowptr = A.rowptr;
         op.col = A.col;
         if (s->fp32) {
@@ -1132,9 +1136,11 @@ __global__ void __launch_bounds__(256) dense_gemv(const T* __restrict__ M, int n
     if (lane == 0) y[row] = acc;
 }
 
-// CSR operator with G lanes per row; the G partial sums are combined by a
-// fixed butterfly inside the group.
-template <class T, int MODE, int G>
+// CSR operator with G lanes per row; each lane takes U entries per pass, their
+// column and value loads issued together ahead of the dependent gathers, so a
+// wavefront keeps several loads in flight per lane.  The G partial sums are
+// combined by a fixed butterfly inside the group.
+template <class T, int MODE, int G, int U>
 __global__ void __launch_bounds__(256) csrv_kernel(const int* __restrict__ rowptr, const int* __restrict__ col,
                                                    const T* __restrict__ val, int n,
                                                    const T* __restrict__ dinv, const T* __restrict__ b,
@@ -1142,12 +1148,24 @@ __global__ void __launch_bounds__(256) csrv_kernel(const int* __restrict__ rowpt
     int gid = blockIdx.x * blockDim.x + threadIdx.x;
     int r = gid / G, l = gid % G;
     if (r >= n) return;
+    const int beg = rowptr[r], end = rowptr[r + 1];
     T acc = 0;
-    for (int e = rowptr[r] + l; e < rowptr[r + 1]; e += G) {
-        int c = col[e];
-        T v = val[e];
-        if (MODE == SV_PRE) acc += v * (dinv[c] * b[c]);
-        else acc += v * x[c];
+    for (int e0 = beg + l; e0 < end; e0 += G * U) {
+        int c[U];
+        T v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            int e = e0 + u * G;
+            c[u] = e < end ? col[e] : -1;
+            v[u] = e < end ? val[e] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (c[u] >= 0) {
+                T xv = MODE == SV_PRE ? dinv[c[u]] * b[c[u]] : x[c[u]];
+                acc += v[u] * xv;
+            }
+        }
     }
 #pragma unroll
     for (int o = G / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, G);
@@ -1164,6 +1182,19 @@ __global__ void __launch_bounds__(256) csrv_kernel(const int* __restrict__ rowpt
     }
 }
 
+template <class T, int MODE, int U>
+static void csrv_launch(dp_sim* s, const Op& op, const T* v, const T* dinv, const T* b, const T* x, T* y,
+                        T* y2) {
+    int grid = ceil_div((int64_t)op.n * op.G, 256);
+    switch (op.G) {
+        case 4: csrv_kernel<T, MODE, 4, U><<<grid, 256, 0, s->stream>>>(op.rowptr, op.col, v, op.n, dinv, b, x, y, y2); break;
+        case 8: csrv_kernel<T, MODE, 8, U><<<grid, 256, 0, s->stream>>>(op.rowptr, op.col, v, op.n, dinv, b, x, y, y2); break;
+        case 16: csrv_kernel<T, MODE, 16, U><<<grid, 256, 0, s->stream>>>(op.rowptr, op.col, v, op.n, dinv, b, x, y, y2); break;
+        case 32: csrv_kernel<T, MODE, 32, U><<<grid, 256, 0, s->stream>>>(op.rowptr, op.col, v, op.n, dinv, b, x, y, y2); break;
+        default: csrv_kernel<T, MODE, 64, U><<<grid, 256, 0, s->stream>>>(op.rowptr, op.col, v, op.n, dinv, b, x, y, y2); break;
+    }
+}
+
 template <class T, int MODE>
 static void op_launch(dp_sim* s, const Op& op, const T* dinv, const T* b, const T* x, T* y, T* y2) {
     if (op.n == 0) return;
@@ -1172,15 +1203,9 @@ static void op_launch(dp_sim* s, const Op& op, const T* dinv, const T* b, const 
         sell_kernel<T, MODE><<<ceil_div(S.n, 256), 256, 0, s->stream>>>(S.sptr, S.col, (const T*)S.val, S.n,
                                                                         dinv, b, x, y, y2);
     } else {
-        int grid = ceil_div((int64_t)op.n * op.G, 256);
         const T* v = (const T*)op.val;
-        switch (op.G) {
-            case 4: csrv_kernel<T, MODE, 4><<<grid, 256, 0, s->stream>>>(op.rowptr, op.col, v, op.n, dinv, b, x, y, y2); break;
-            case 8: csrv_kernel<T, MODE, 8><<<grid, 256, 0, s->stream>>>(op.rowptr, op.col, v, op.n, dinv, b, x, y, y2); break;
-            case 16: csrv_kernel<T, MODE, 16><<<grid, 256, 0, s->stream>>>(op.rowptr, op.col, v, op.n, dinv, b, x, y, y2); break;
-            case 32: csrv_kernel<T, MODE, 32><<<grid, 256, 0, s->stream>>>(op.rowptr, op.col, v, op.n, dinv, b, x, y, y2); break;
-            default: csrv_kernel<T, MODE, 64><<<grid, 256, 0, s->stream>>>(op.rowptr, op.col, v, op.n, dinv, b, x, y, y2); break;
-        }
+        if (op.U != 2) throw Error(DP_E_INVALID, "CSR operator built for another unroll");
+        csrv_launch<T, MODE, 2>(s, op, v, dinv, b, x, y, y2);
     }
     DP_LAUNCH_CHECK();
 }

@@ -10,7 +10,7 @@
 //     stay inside their own index ranges, so groups need no merge;
 //   * a row that does not fit its group is handled alone by the wavefront when
 //     it has at most SW_MAX terms, else listed for 256-thread workgroups that
-//     take up to SM_MAX terms (24 KB of LDS), then up to SB_MAX (96 KB);
+//     take up to SM_MAX terms (25 KB of LDS), then up to SB_MAX (101 KB);
 //   * a longer row makes the call return false (the caller then takes the
 //     global radix-sort path).
 // Sorting is a bitonic network on 64-bit keys; sums, compaction ranks (ballot
@@ -22,8 +22,8 @@
 namespace dp {
 
 constexpr int SW_MAX = 256;
-constexpr int SM_MAX = 1024;  // 24 KB of LDS per workgroup
-constexpr int SB_MAX = 4096;  // 96 KB of LDS per workgroup
+constexpr int SM_MAX = 1024;  // 25 KB of LDS per workgroup
+constexpr int SB_MAX = 4096;  // 101 KB of LDS per workgroup
 constexpr int SEG_TARGET = 128;  // terms per wavefront group
 constexpr int SEG_GMAX = 64;     // rows per group
 
@@ -33,8 +33,9 @@ struct SegTile {
     static_assert((MAXE & (MAXE - 1)) == 0, "tile size must be a power of two");
     uint64_t key[MAXE];
     double v[MAXE];       // term values in term order; run sums at run heads
-    int rank[MAXE + 1];
+    int rank[MAXE + 1];   // product mode, before the sort: Y row start of every X entry
     int eo[MAXE + 1];     // product mode: term offset of every X entry of the tile
+    unsigned char erow[MAXE];  // product mode: tile-local row of every X entry
     int64_t rowoff[SEG_GMAX + 1];  // term offsets of the tile's rows
     int xoff[SEG_GMAX + 1];        // product mode: X entry offsets of the tile's rows
 };
@@ -90,17 +91,23 @@ __device__ void tile_run(SegTile<MAXE>& T, const Src& S, int ra, int rb, int64_t
     const int total = (int)(T.rowoff[nr] - base);
     const int P2 = max(2 * NT, pow2ceil(total));
     if constexpr (PROD) {
-        // term offsets of the tile's X entries (wave 0, 64 at a time)
+        // every X entry of the tile, all threads: its Y row start and term count
+        // (one round of dependent loads) and its tile-local row, kept in LDS
         const int e0 = T.xoff[0], ne = T.xoff[nr] - e0;
+        for (int j = tid; j < ne; j += NT) {
+            int k = S.X.col[e0 + j];
+            int a = S.Y.rowptr[k];
+            T.eo[j] = S.Y.rowptr[k + 1] - a;
+            T.rank[j] = a;
+            T.erow[j] = (unsigned char)upper_idx(T.xoff, nr, e0 + j);
+        }
+        __syncthreads();
+        // exclusive scan of the term counts into term offsets (wave 0, 64 at a time)
         if (tid < WAVE) {
             int run = 0;
             for (int c0 = 0; c0 < ne; c0 += WAVE) {
                 int j = c0 + tid;
-                int len = 0;
-                if (j < ne) {
-                    int k = S.X.col[e0 + j];
-                    len = S.Y.rowptr[k + 1] - S.Y.rowptr[k];
-                }
+                int len = j < ne ? T.eo[j] : 0;
                 int x = len;
 #pragma unroll
                 for (int o = 1; o < WAVE; o <<= 1) {
@@ -115,18 +122,16 @@ __device__ void tile_run(SegTile<MAXE>& T, const Src& S, int ra, int rb, int64_t
         __syncthreads();
         for (int t = tid; t < P2; t += NT) {
             if (t < total) {
+                // entries with no terms have equal offsets: upper_idx gives the last one
                 int j = upper_idx(T.eo, ne, t);
-                // skip entries with no terms (equal offsets): upper_idx gives the last one
-                int e = e0 + j;
-                int rl = upper_idx(T.xoff, nr, e);
-                int k = S.X.col[e];
-                int f = S.Y.rowptr[k] + (t - T.eo[j]);
-                T.key[t] = ((uint64_t)rl << 40) | ((uint64_t)(uint32_t)S.Y.col[f] << IB) | (uint64_t)t;
-                T.v[t] = S.X.val[e] * S.Y.val[f];
+                int f = T.rank[j] + (t - T.eo[j]);
+                T.key[t] = ((uint64_t)T.erow[j] << 40) | ((uint64_t)(uint32_t)S.Y.col[f] << IB) | (uint64_t)t;
+                T.v[t] = S.X.val[e0 + j] * S.Y.val[f];
             } else {
                 T.key[t] = ~0ull;
             }
         }
+        __syncthreads();  // the sums below overwrite rank
     } else {
         for (int t = tid; t < P2; t += NT) {
             if (t < total) {

@@ -84,8 +84,8 @@ struct Sell {
 // An operator of the V-cycle in the apply precision: SELL-64 when its rows are
 // short and even, else CSR processed by G lanes per row.
 struct Op {
-    int kind = 0;  // 0 SELL-64, 1 CSR with G lanes per row
-    int n = 0, G = 4;
+    int kind = 0;  // 0 SELL-64, 1 CSR with G lanes per row, U entries per lane and pass
+    int n = 0, G = 4, U = 1;
     int64_t nnz = 0;
     Sell s;
     int* rowptr = nullptr;
