@@ -574,12 +574,16 @@ __device__ __forceinline__ void gj_step(double (&a)[GJ_B], int* bad) {
     }
     p = __builtin_amdgcn_readlane(p, C);
     if (lane_bcast(best, C) == 0.0 && threadIdx.x == 0) *bad = 1;
+    // p is the same on every lane: the swap is skipped as a whole when the
+    // diagonal entry is already the pivot (written as selects so that the array
+    // stays in registers)
+    if (p != C) {
 #pragma unroll
-    for (int r = C + 1; r < GJ_B; ++r) {
-        if (r == p) {
-            double t = a[C];
-            a[C] = a[r];
-            a[r] = t;
+        for (int r = C + 1; r < GJ_B; ++r) {
+            const bool sw = r == p;
+            const double ac = a[C], ar = a[r];
+            a[C] = sw ? ar : ac;
+            a[r] = sw ? ac : ar;
         }
     }
     double inv = 1.0 / lane_bcast(a[C], C);
