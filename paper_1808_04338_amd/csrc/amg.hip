@@ -81,6 +81,11 @@ __device__ inline int rl_or(int v) {
     for (int o = RL / 2; o > 0; o >>= 1) v |= __shfl_xor(v, o, RL);
     return v;
 }
+__device__ inline int rl_isum(int v) {
+#pragma unroll
+    for (int o = RL / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, RL);
+    return v;
+}
 inline int rl_grid(int n) { return ceil_div((int64_t)n * RL, 256); }
 
 __global__ void strength_kernel(Csr A, double theta, unsigned char* smask, int* nst, double* diag) {
@@ -127,12 +132,16 @@ __global__ void pmis_init(int n, const int* __restrict__ nst, int* state, double
 
 // For every strong edge with both ends undecided, the end with the smaller
 // (weight, index) is beaten in this iteration.
+// RL lanes per row: every undecided neighbour pair through a strong edge marks
+// the loser (the lower weight, ties to the lower index) as beaten this iteration
+// (all writers store the same value).
 __global__ void pmis_beat(Csr A, const unsigned char* __restrict__ smask, const int* __restrict__ state,
                           const double* __restrict__ wgt, int iter, int* beaten) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= A.n || state[i] != ST_U) return;
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    int i = g / RL, l = g % RL;
+    if (i >= A.n || state[i] != ST_U) return;  // whole subgroup
     double wi = wgt[i];
-    for (int e = A.rowptr[i]; e < A.rowptr[i + 1]; ++e) {
+    for (int e = A.rowptr[i] + l; e < A.rowptr[i + 1]; e += RL) {
         if (!smask[e]) continue;
         int j = A.col[e];
         if (state[j] != ST_U) continue;
@@ -149,21 +158,27 @@ __global__ void pmis_select(int n, int* state, const int* __restrict__ beaten, i
     if (beaten[i] != iter) state[i] = C_BASE + iter;
 }
 
-// Undecided points that depend strongly on a C point of this iteration become F.
+// Undecided points that depend strongly on a C point of this iteration become F
+// (RL lanes per row; a C state of this iteration does not change in this pass).
 __global__ void pmis_fpass(Csr A, const unsigned char* __restrict__ smask, int* state, int iter,
                            int* undecided) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    int i = g / RL, l = g % RL;
     bool und = false;
-    if (i < A.n && state[i] == ST_U) {
-        bool f = false;
-        for (int e = A.rowptr[i]; e < A.rowptr[i + 1]; ++e)
-            if (smask[e] && state[A.col[e]] == C_BASE + iter) f = true;
-        if (f) state[i] = ST_F;
-        else und = true;
+    if (i < A.n && state[i] == ST_U) {  // whole subgroup
+        int f = 0;
+        for (int e = A.rowptr[i] + l; e < A.rowptr[i + 1]; e += RL)
+            if (smask[e] && state[A.col[e]] == C_BASE + iter) f = 1;
+        f = rl_or(f);
+        if (l == 0) {
+            if (f) state[i] = ST_F;
+            else und = true;
+        }
     }
-    // one atomic per wavefront
+    // a flag, not a count: the host only asks whether any point is undecided
+    // (every writer stores 1; no atomic serialises the wavefronts)
     uint64_t m = __ballot(und);
-    if (threadIdx.x % WAVE == 0 && m) atomicAdd(undecided, (int)__popcll(m));
+    if (threadIdx.x % WAVE == 0 && m) *undecided = 1;
 }
 
 __global__ void pmis_final(int n, const int* __restrict__ state, int* cf, int64_t* cflag) {
@@ -183,13 +198,14 @@ __global__ void pmis_final(int n, const int* __restrict__ state, int* cf, int64_
 // ---------------------------------------------------------------------------
 __global__ void interp_beta(Csr A, const unsigned char* __restrict__ smask, const int* __restrict__ cf,
                             const double* __restrict__ diag, double* beta, int* g) {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= A.n) return;
+    int gi = blockIdx.x * blockDim.x + threadIdx.x;
+    int k = gi / RL, l = gi % RL;
+    if (k >= A.n) return;  // whole subgroup
     double bsum = 0.0;
     int cnt = 0;
     if (cf[k] < 0) {
         double dk = diag[k];
-        for (int e = A.rowptr[k]; e < A.rowptr[k + 1]; ++e) {
+        for (int e = A.rowptr[k] + l; e < A.rowptr[k + 1]; e += RL) {
             int j = A.col[e];
             double v = A.val[e];
             if (smask[e] && cf[j] > 0 && v * dk < 0.0) {
@@ -198,8 +214,12 @@ __global__ void interp_beta(Csr A, const unsigned char* __restrict__ smask, cons
             }
         }
     }
-    beta[k] = bsum;
-    g[k] = cnt;
+    bsum = rl_sum(bsum);
+    cnt = rl_isum(cnt);
+    if (l == 0) {
+        beta[k] = bsum;
+        g[k] = cnt;
+    }
 }
 
 // Row of every stored entry (thread per row).
@@ -214,21 +234,19 @@ __global__ void entry_rows(Csr A, int* erow) {
 // cannot distribute (beta_k = 0); weak entries first, then those, column order.
 __global__ void interp_d(Csr A, const unsigned char* __restrict__ smask, const int* __restrict__ cf,
                          const double* __restrict__ diag, const double* __restrict__ beta, double* dd) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= A.n) return;
-    double d = diag[i];
+    int gi = blockIdx.x * blockDim.x + threadIdx.x;
+    int i = gi / RL, l = gi % RL;
+    if (i >= A.n) return;  // whole subgroup
+    double s = 0.0;
     if (cf[i] < 0) {
-        int b = A.rowptr[i], e1 = A.rowptr[i + 1];
-        for (int e = b; e < e1; ++e) {
+        for (int e = A.rowptr[i] + l; e < A.rowptr[i + 1]; e += RL) {
             int j = A.col[e];
-            if (j != i && !smask[e]) d += A.val[e];
-        }
-        for (int e = b; e < e1; ++e) {
-            int j = A.col[e];
-            if (j != i && smask[e] && cf[j] < 0 && beta[j] == 0.0) d += A.val[e];
+            if (j == i) continue;
+            if (!smask[e] || (cf[j] < 0 && beta[j] == 0.0)) s += A.val[e];
         }
     }
-    dd[i] = d;
+    s = rl_sum(s);
+    if (l == 0) dd[i] = diag[i] + s;
 }
 
 // Number of products each stored entry (i, k) of an F row contributes to row i
@@ -914,7 +932,7 @@ void amg_setup(dp_sim* s) {
             int* state = Sc.get<int>(n, "pmis state");
             double* wgt = Sc.get<double>(n, "pmis weight");
             int* beaten = Sc.get<int>(n, "pmis beaten");
-            int* und = Sc.get<int>(PMIS_BATCH, "pmis count");
+            int* und = Sc.get<int>(PMIS_BATCH, "pmis undecided flags");
             cidx = Sc.get<int64_t>(n + 1, "coarse index");
             int64_t* stmp = Sc.get<int64_t>(scan_tmp_size(n + 1), "scan tmp");
             L.cf = H.get<int>(n, "cf");
@@ -929,9 +947,9 @@ void amg_setup(dp_sim* s) {
                 if (iter > 10000) fail(DP_E_NUMERIC, "PMIS did not terminate");
                 DP_HIP(hipMemsetAsync(und, 0, sizeof(int) * PMIS_BATCH, st));
                 for (int b = 0; b < PMIS_BATCH; ++b, ++iter) {
-                    pmis_beat<<<ceil_div(n, 256), 256, 0, st>>>(A, smask, state, wgt, iter, beaten);
+                    pmis_beat<<<rl_grid(n), 256, 0, st>>>(A, smask, state, wgt, iter, beaten);
                     pmis_select<<<ceil_div(n, 256), 256, 0, st>>>(n, state, beaten, iter);
-                    pmis_fpass<<<ceil_div(n, 256), 256, 0, st>>>(A, smask, state, iter, und + b);
+                    pmis_fpass<<<rl_grid(n), 256, 0, st>>>(A, smask, state, iter, und + b);
                 }
                 DP_LAUNCH_CHECK();
                 int hu = 0;
@@ -963,8 +981,8 @@ void amg_setup(dp_sim* s) {
             int64_t* ecnt = Sc.get<int64_t>(A.nnz + 1, "interp entry count");
             int64_t* etmp = Sc.get<int64_t>(scan_tmp_size(A.nnz + 1), "scan tmp");
             entry_rows<<<rl_grid(n), 256, 0, st>>>(A, erow);
-            interp_beta<<<ceil_div(n, 256), 256, 0, st>>>(A, smask, L.cf, diag, beta, g);
-            interp_d<<<ceil_div(n, 256), 256, 0, st>>>(A, smask, L.cf, diag, beta, dd);
+            interp_beta<<<rl_grid(n), 256, 0, st>>>(A, smask, L.cf, diag, beta, g);
+            interp_d<<<rl_grid(n), 256, 0, st>>>(A, smask, L.cf, diag, beta, dd);
             interp_count_e<<<ceil_div(A.nnz, 256), 256, 0, st>>>(A, erow, smask, L.cf, beta, g, ecnt);
             DP_LAUNCH_CHECK();
             int64_t m = 0;
