@@ -435,14 +435,44 @@ __global__ void pfill_kernel(Csr W, const int* __restrict__ cf, const int64_t* _
 }
 
 // ---------------------------------------------------------------------------
-// Transpose and Galerkin product by expansion + stable sort + ordered sums
+// Galerkin product by expansion + stable sort + ordered sums (fallback path)
 // ---------------------------------------------------------------------------
-__global__ void transpose_expand(Csr P, int rbits, uint64_t* keys, double* vals) {
+// Transpose R = P^T by counting: entries per column, offsets, a scatter with a
+// cursor per column, then every R row sorted by its column (the fine row) in
+// the segmented tiles.  Keys are unique within a row, so the result does not
+// depend on the order the scatter wrote it in.
+__global__ void transpose_count(Csr P, unsigned long long* cnt) {
+    int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < P.nnz) atomicAdd(&cnt[P.col[e]], 1ull);
+}
+
+__global__ void transpose_scatter(Csr P, const int64_t* __restrict__ roff, int* cur, int* rcol, double* rval) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= P.n) return;
     for (int e = P.rowptr[i]; e < P.rowptr[i + 1]; ++e) {
-        keys[e] = ((uint64_t)P.col[e] << rbits) | (uint64_t)i;
-        vals[e] = P.val[e];
+        int c = P.col[e];
+        int64_t pos = roff[c] + atomicAdd(&cur[c], 1);
+        rcol[pos] = i;
+        rval[pos] = P.val[e];
+    }
+}
+
+// Fallback for rows beyond the segmented tiles: insertion sort, one thread per row.
+__global__ void transpose_sort_rows(int nr, const int64_t* __restrict__ roff, int* rcol, double* rval) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nr) return;
+    int64_t b = roff[r], e1 = roff[r + 1];
+    for (int64_t a = b + 1; a < e1; ++a) {
+        int c = rcol[a];
+        double v = rval[a];
+        int64_t q = a;
+        while (q > b && rcol[q - 1] > c) {
+            rcol[q] = rcol[q - 1];
+            rval[q] = rval[q - 1];
+            --q;
+        }
+        rcol[q] = c;
+        rval[q] = v;
     }
 }
 
@@ -1042,26 +1072,44 @@ void amg_setup(dp_sim* s) {
             DP_LAUNCH_CHECK();
         }
         Sc.top = smark;
-        // R = P^T
+        // R = P^T (counting transpose, rows sorted in the segmented tiles)
         Csr R;
         {
             int64_t m = L.P.nnz;
-            int rbits = bits_for(n);
-            int cb = bits_for(nc);
-            uint64_t* k0 = Sc.get<uint64_t>(m, "PT keys");
-            double* v0 = Sc.get<double>(m, "PT vals");
-            uint64_t* k1 = Sc.get<uint64_t>(m, "PT keys");
-            double* v1 = Sc.get<double>(m, "PT vals");
-            int64_t* rtmp = Sc.get<int64_t>(sort_tmp_size(m) + scan_tmp_size(m + 1), "sort tmp");
-            transpose_expand<<<ceil_div(n, 256), 256, 0, st>>>(L.P, rbits, k0, v0);
-            DP_LAUNCH_CHECK();
-            int which = radix_sort(st, k0, v0, k1, v1, m, rbits + cb, rtmp);
-            int64_t* flag = (int64_t*)(which ? k0 : k1);
-            double* sums = which ? v0 : v1;
-            int* rowkey = Sc.get<int>(m, "rbk rows");
+            int64_t* roff = Sc.get<int64_t>(nc + 1, "PT offsets");
+            int64_t* stmp = Sc.get<int64_t>(scan_tmp_size(nc + 1), "scan tmp");
+            int* cur = Sc.get<int>(nc, "PT cursors");
+            int* tcol = Sc.get<int>(m, "PT terms");
+            double* tval = Sc.get<double>(m, "PT terms");
+            DP_HIP(hipMemsetAsync(roff, 0, sizeof(int64_t) * (nc + 1), st));
+            DP_HIP(hipMemsetAsync(cur, 0, sizeof(int) * (nc > 0 ? nc : 1), st));
+            if (m > 0) {
+                transpose_count<<<ceil_div(m, 256), 256, 0, st>>>(L.P, (unsigned long long*)roff);
+                DP_LAUNCH_CHECK();
+            }
+            scan_inplace(st, roff, nc + 1, stmp);
+            if (m > 0) {
+                transpose_scatter<<<ceil_div(n, 256), 256, 0, st>>>(L.P, roff, cur, tcol, tval);
+                DP_LAUNCH_CHECK();
+            }
             R.ncols = n;
-            reduce_to_csr(st, which ? k1 : k0, which ? v1 : v0, m, rbits, nc, flag, sums, rowkey, rtmp,
-                          H, R, "R");
+            if (!seg_sort_reduce(st, roff, nc, n, tcol, tval, m, Sc, H, R, "R")) {
+                // rows beyond the tiles: scatter again (the tiles rewrite the rows they
+                // finished in place), sort in place and take the arrays as R
+                DP_HIP(hipMemsetAsync(cur, 0, sizeof(int) * (nc > 0 ? nc : 1), st));
+                if (m > 0) transpose_scatter<<<ceil_div(n, 256), 256, 0, st>>>(L.P, roff, cur, tcol, tval);
+                transpose_sort_rows<<<ceil_div(nc, 256), 256, 0, st>>>(nc, roff, tcol, tval);
+                DP_LAUNCH_CHECK();
+                R.n = nc;
+                R.nnz = m;
+                R.rowptr = H.get<int>(nc + 1, "R");
+                R.col = H.get<int>(m, "R");
+                R.val = H.get<double>(m, "R");
+                i64_to_i32<<<ceil_div(nc + 1, 256), 256, 0, st>>>(roff, nc, m, R.rowptr);
+                DP_LAUNCH_CHECK();
+                DP_HIP(hipMemcpyAsync(R.col, tcol, sizeof(int) * m, hipMemcpyDeviceToDevice, st));
+                DP_HIP(hipMemcpyAsync(R.val, tval, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
+            }
         }
         Sc.top = smark;
         // Galerkin A_c = R (A P), both products row by row

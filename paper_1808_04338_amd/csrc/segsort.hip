@@ -286,15 +286,21 @@ __global__ void seg_rowptr(const int64_t* __restrict__ c, int n, int64_t total, 
 __global__ void seg_set_last(int64_t* off, int n, int64_t m) { off[n] = m; }
 
 // terms of row r of X Y
+// Terms of every product row, PCL lanes per row (row lengths reach 50 on the
+// coarse levels).
+constexpr int PCL = 8;
 __global__ void prod_count(Csr X, Csr Y, int64_t* cnt) {
-    int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= X.n) return;
-    int64_t c = 0;
-    for (int e = X.rowptr[r]; e < X.rowptr[r + 1]; ++e) {
+    int g = blockIdx.x * blockDim.x + threadIdx.x;
+    int r = g / PCL, l = g % PCL;
+    if (r >= X.n) return;  // whole subgroup
+    long long c = 0;
+    for (int e = X.rowptr[r] + l; e < X.rowptr[r + 1]; e += PCL) {
         int k = X.col[e];
         c += Y.rowptr[k + 1] - Y.rowptr[k];
     }
-    cnt[r] = c;
+#pragma unroll
+    for (int o = PCL / 2; o > 0; o >>= 1) c += __shfl_xor(c, o, PCL);
+    if (l == 0) cnt[r] = c;
 }
 
 // Shared driver: runs the tiles, then scans the row lengths and copies the
@@ -370,7 +376,7 @@ bool seg_product(hipStream_t st, const Csr& X, const Csr& Y, Arena& sc, Arena& o
     int64_t* tmp = sc.get<int64_t>(scan_tmp_size(nrows + 1), "scan tmp");
     int64_t m = 0;
     if (nrows > 0) {
-        prod_count<<<ceil_div(nrows, 256), 256, 0, st>>>(X, Y, off);
+        prod_count<<<ceil_div((int64_t)nrows * PCL, 256), 256, 0, st>>>(X, Y, off);
         DP_LAUNCH_CHECK();
         exclusive_scan(st, off, nrows, tmp, &m);
     }
