@@ -295,11 +295,46 @@ __global__ void interp_expand_e(Csr A, const int* __restrict__ erow, const unsig
     }
 }
 
+// Distance-two pieces of every F row k with beta_k != 0: its strong C
+// neighbours j with a_kj a_kk < 0, as (coarse index, a_kj / beta_k), in row
+// order at goff[k] (RL lanes per row; a ballot prefix count keeps the order).
+__global__ void interp_pieces(Csr A, const unsigned char* __restrict__ smask, const int* __restrict__ cf,
+                              const int64_t* __restrict__ cidx, const double* __restrict__ diag,
+                              const double* __restrict__ beta, const int64_t* __restrict__ goff, int* pcol,
+                              double* pval) {
+    int gi = blockIdx.x * blockDim.x + threadIdx.x;
+    int k = gi / RL, l = gi % RL;
+    if (k >= A.n || cf[k] > 0 || beta[k] == 0.0) return;  // whole subgroup
+    const double bk = beta[k], dk = diag[k];
+    const int sub0 = (int)(threadIdx.x % WAVE) - l;
+    int64_t o = goff[k];
+    for (int fb = A.rowptr[k]; fb < A.rowptr[k + 1]; fb += RL) {
+        int f = fb + l;
+        bool take = false;
+        int jj = 0;
+        double v = 0.0;
+        if (f < A.rowptr[k + 1]) {
+            jj = A.col[f];
+            v = A.val[f];
+            take = smask[f] && cf[jj] > 0 && v * dk < 0.0;
+        }
+        uint64_t mine = (__ballot(take) >> sub0) & ((1ull << RL) - 1);
+        if (take) {
+            int64_t q = o + __popcll(mine & ((1ull << l) - 1));
+            pcol[q] = (int)cidx[jj];
+            pval[q] = v / bk;
+        }
+        o += __popcll(mine);
+    }
+}
+
 // The same interpolation terms as column/value pairs (the segmented path):
-// terms of F row i are contiguous because A's entries are grouped by row.
+// terms of F row i are contiguous because A's entries are grouped by row.  A
+// strong F neighbour k contributes a_ik times each of its pieces.
 __global__ void interp_expand_c(Csr A, const int* __restrict__ erow, const unsigned char* __restrict__ smask,
                                 const int* __restrict__ cf, const int64_t* __restrict__ cidx,
-                                const double* __restrict__ diag, const double* __restrict__ beta,
+                                const double* __restrict__ beta, const int64_t* __restrict__ goff,
+                                const int* __restrict__ pcol, const double* __restrict__ pval,
                                 const int64_t* __restrict__ off, int* cols, double* vals) {
     int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= A.nnz) return;
@@ -312,17 +347,17 @@ __global__ void interp_expand_c(Csr A, const int* __restrict__ erow, const unsig
         cols[o] = (int)cidx[j];
         vals[o] = a;
     } else if (beta[j] != 0.0) {
-        double bk = beta[j], dk = diag[j];
-        for (int f = A.rowptr[j]; f < A.rowptr[j + 1]; ++f) {
-            int jj = A.col[f];
-            double v = A.val[f];
-            if (smask[f] && cf[jj] > 0 && v * dk < 0.0) {
-                cols[o] = (int)cidx[jj];
-                vals[o] = a * (v / bk);
-                ++o;
-            }
+        for (int64_t t = goff[j]; t < goff[j + 1]; ++t, ++o) {
+            cols[o] = pcol[t];
+            vals[o] = a * pval[t];
         }
     }
+}
+
+// a[0..n) widened to int64 with a[n] = 0 (for an exclusive scan that leaves the total there)
+__global__ void int_to_i64(const int* __restrict__ a, int n, int64_t* b) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i <= n) b[i] = i < n ? (int64_t)a[i] : 0;
 }
 
 // Row offsets of terms generated per matrix entry: row r starts where its first
@@ -1026,8 +1061,16 @@ void amg_setup(dp_sim* s) {
                 int* wc = Sc.get<int>(m, "interp terms");
                 double* wv = Sc.get<double>(m, "interp terms");
                 int64_t* woff = Sc.get<int64_t>(n + 1, "interp rows");
-                interp_expand_c<<<ceil_div(A.nnz, 256), 256, 0, st>>>(A, erow, smask, L.cf, cidx, diag, beta,
-                                                                      ecnt, wc, wv);
+                // pieces of every F row: offsets from g (a device-only scan; at most nnz)
+                int64_t* goff = Sc.get<int64_t>(n + 1, "interp piece offsets");
+                int* pcol = Sc.get<int>(A.nnz, "interp pieces");
+                double* pval = Sc.get<double>(A.nnz, "interp pieces");
+                int_to_i64<<<ceil_div(n + 1, 256), 256, 0, st>>>(g, n, goff);
+                DP_LAUNCH_CHECK();
+                scan_inplace(st, goff, n + 1, stmp);
+                interp_pieces<<<rl_grid(n), 256, 0, st>>>(A, smask, L.cf, cidx, diag, beta, goff, pcol, pval);
+                interp_expand_c<<<ceil_div(A.nnz, 256), 256, 0, st>>>(A, erow, smask, L.cf, cidx, beta, goff, pcol,
+                                                                      pval, ecnt, wc, wv);
                 seg_off_from_entries<<<ceil_div(n + 1, 256), 256, 0, st>>>(A.rowptr, ecnt, n, A.nnz, m, woff);
                 DP_LAUNCH_CHECK();
                 done = seg_sort_reduce(st, woff, n, nc, wc, wv, m, Sc, Sc, W, "interp W");
