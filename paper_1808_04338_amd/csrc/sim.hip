@@ -52,6 +52,7 @@ static void validate(const dp_sim_desc& d) {
     if (d.forcing < 0 || d.forcing > 3) fail(DP_E_INVALID, "forcing must be 0, 1, 2 or 3");
     if (d.precond_eager < 0 || d.precond_eager > 2) fail(DP_E_INVALID, "precond_eager must be 0, 1 or 2");
     if (d.decoupling < DP_DEC_GJ || d.decoupling > DP_DEC_TI) fail(DP_E_INVALID, "bad decoupling");
+    if (!std::isfinite(d.c_r)) fail(DP_E_INVALID, "rock compressibility must be finite");
     if (d.cpr_variant != DP_CPR_FPF && d.cpr_variant != DP_CPR_FP) fail(DP_E_INVALID, "bad cpr_variant");
     if (d.forcing && !(d.forcing_beta > 1.0 && d.forcing_beta <= 2.0 && d.forcing_gamma <= 1.0 &&
                        d.forcing_eta_min <= d.forcing_eta_max && d.forcing_eta_max < 1.0))

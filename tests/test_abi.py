@@ -104,6 +104,41 @@ def test_invalid_descriptors_are_rejected():
         footprint(m, gmres_restart=64)
 
 
+def test_invalid_solver_variants_and_well_options_are_rejected():
+    """Descriptor fields the Python mapping cannot produce (set directly on the
+    struct) and well options that do not fit the well kind fail in the host-only
+    validation with DP_E_INVALID."""
+    import ctypes as C
+
+    from paper_1808_04338_amd import _lib as L
+    from paper_1808_04338_amd import footprint
+    from paper_1808_04338_amd.sim import make_desc
+
+    lib = L.load()
+    m = synth.model_small()
+    for field, val in (("decoupling", 3), ("decoupling", -1), ("cpr_variant", 2), ("c_r", float("nan")),
+                       ("c_r", float("inf"))):
+        d, keep = make_desc(m, None)
+        setattr(d, field, val)
+        nbytes = C.c_size_t()
+        assert lib.sim_footprint(C.byref(d), C.byref(nbytes)) == L.DP_E_INVALID, (field, val)
+    for bad in (dict(m["wells"][0], control="orate"),  # oil-rate control on an injector
+                dict(m["wells"][0], wi=-1.0),
+                dict(m["wells"][0], wi=float("nan"))):
+        with pytest.raises(L.DpError) as e:
+            footprint(dict(m, wells=[bad] + m["wells"][1:]))
+        assert e.value.code == L.DP_E_INVALID
+    prod = dict(m["wells"][1], control="rate")  # water-rate control on a producer
+    with pytest.raises(L.DpError):
+        footprint(dict(m, wells=[m["wells"][0], prod]))
+    # the valid variants pass
+    for dec in ("gj", "abf", "ti"):
+        for cpr in ("fpf", "fp"):
+            assert footprint(m, decoupling=dec, cpr_variant=cpr) > 0
+    ok = dict(m["wells"][1], control="orate", target=1e-3, bhp_limit=1e6)
+    assert footprint(dict(m, wells=[m["wells"][0], ok], c_r=4e-10)) > 0
+
+
 def test_create_rejects_null_workspace_without_touching_a_gpu():
     L, lib = _lib()
     from paper_1808_04338_amd.sim import _dp, make_desc
