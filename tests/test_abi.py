@@ -108,8 +108,6 @@ def test_invalid_solver_variants_and_well_options_are_rejected():
     """Descriptor fields the Python mapping cannot produce (set directly on the
     struct) and well options that do not fit the well kind fail in the host-only
     validation with DP_E_INVALID."""
-    import ctypes as C
-
     from paper_1808_04338_amd import _lib as L
     from paper_1808_04338_amd import footprint
     from paper_1808_04338_amd.sim import make_desc
