@@ -14,6 +14,7 @@ import argparse
 import json
 import os
 import sys
+import threading
 import time
 
 import numpy as np
@@ -169,7 +170,17 @@ def served_leg(count):
     stream = synth.served_stream(count=count)
     reqs = [Request(r, synth.served_realisation(r, size), t, tag="%dx%dx%d" % size)
             for t, r, size in stream]
-    res, summ = serve(reqs, budget_bytes=200 << 30, precision="fp32")
+    done = [0]
+    lock = threading.Lock()
+
+    def on_done(r):
+        with lock:
+            done[0] += 1
+            k = done[0]
+        log("served %d/%d finished: request %d (%s), %d steps, %s" % (k, len(reqs), r.rid, r.tag,
+                                                                      len(r.latencies), r.status))
+
+    res, summ = serve(reqs, budget_bytes=200 << 30, precision="fp32", on_done=on_done)
     summ["unit"] = "timesteps/s"
     summ["failures"] = [{"rid": r.rid, "class": r.tag, "steps_done": len(r.latencies),
                          "error": r.error} for r in res.values() if r.status != "ok"]

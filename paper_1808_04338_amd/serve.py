@@ -46,11 +46,13 @@ class Result:
 
 
 def serve(requests, budget_bytes=200 << 30, max_active=64, precision="fp32", device="cuda:0",
-          keep_state=False, clock=time.perf_counter, sim_factory=None, footprint_fn=None, **sim_opts):
+          keep_state=False, clock=time.perf_counter, sim_factory=None, footprint_fn=None, on_done=None,
+          **sim_opts):
     """Run the requests; returns (results by rid, summary dict).
 
     sim_factory(model) -> handle and footprint_fn(model) -> bytes default to the
-    library's Sim on its own stream and sim_footprint."""
+    library's Sim on its own stream and sim_footprint.  on_done(result), if
+    given, is called from the request's worker thread when it finishes."""
     if sim_factory is None:
         import torch
 
@@ -99,6 +101,8 @@ def serve(requests, budget_bytes=200 << 30, max_active=64, precision="fp32", dev
                 state["used"] -= fp
                 state["active"] -= 1
                 lock.notify_all()
+            if on_done is not None:
+                on_done(res)
 
     while pending or waiting:
         t = now()

@@ -60,3 +60,21 @@ def test_oversized_request_rejected_others_served():
     assert res[0].status == "rejected"
     assert res[1].status == "ok"
     assert summ["rejected"] == 1 and summ["completed"] == 1
+
+
+def test_completion_hook_runs_once_per_served_request():
+    """on_done sees every admitted request once, after its last step; a rejected
+    request never reaches a worker, so it is not reported."""
+    seen = []
+    lock = threading.Lock()
+
+    def on_done(r):
+        with lock:
+            seen.append((r.rid, len(r.latencies), r.status))
+
+    reqs = [Request(i, _model("m%d" % i, 2, 1), 0.001 * i) for i in range(6)]
+    reqs.append(Request(6, _model("big", 50, 1), 0.0))
+    res, summ = serve(reqs, budget_bytes=10, max_active=2, sim_factory=FakeSim,
+                      footprint_fn=lambda m: m["fp"], on_done=on_done)
+    assert sorted(seen) == [(i, 3, "ok") for i in range(6)]
+    assert res[6].status == "rejected"
