@@ -729,31 +729,11 @@ __device__ inline d4v mfma_tile(const double* X, int64_t ldx, const double* Y, i
     return acc;
 }
 
-// The same 32x32 tile product with plain FMAs and the MFMA output layout
-// (reference path, selected with DPSIM_GJ_PLAIN=1).
-__device__ inline d4v fma_tile(const double* X, int64_t ldx, const double* Y, int64_t ldy, int qr,
-                               int qc) {
-    d4v acc = {0.0, 0.0, 0.0, 0.0};
-    for (int i = 0; i < 4; ++i) {
-        int r, c;
-        tile_rc(i, qr, qc, r, c);
-        double s = 0.0;
-        for (int k = 0; k < GJ_B; ++k) s += X[(int64_t)r * ldx + k] * Y[(int64_t)k * ldy + c];
-        acc[i] = s;
-    }
-    return acc;
-}
-
-template <bool MF>
-__device__ inline d4v tile_mm(const double* X, int64_t ldx, const double* Y, int64_t ldy, int qr, int qc) {
-    return MF ? mfma_tile(X, ldx, Y, ldy, qr, qc) : fma_tile(X, ldx, Y, ldy, qr, qc);
-}
 
 
 
 // Row panel k: M_kj <- P M_kj (j != k).  Also copies the old column panel
 // M_ik into Cbuf (np x 32).
-template <bool MF>
 __global__ void __launch_bounds__(256) gj_row(double* M, int np, int kb, const double* __restrict__ P,
                                               double* Cbuf) {
     int nbk = np / GJ_B;
@@ -764,7 +744,7 @@ __global__ void __launch_bounds__(256) gj_row(double* M, int np, int kb, const d
         int jb = tile;
         if (jb == kb) return;
         double* Y = M + (int64_t)kb * GJ_B * np + jb * GJ_B;
-        d4v acc = tile_mm<MF>(P, GJ_B, Y, np, qr, qc);
+        d4v acc = mfma_tile(P, GJ_B, Y, np, qr, qc);
         __syncthreads();  // every wave has read its operands of Y before any write
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -783,7 +763,6 @@ __global__ void __launch_bounds__(256) gj_row(double* M, int np, int kb, const d
 
 // All tiles (i, j) with i != k: M_ij -= C_i M_kj (j != k), M_ik = -C_i P.
 // Tile (k, k) becomes P.
-template <bool MF>
 __global__ void __launch_bounds__(256) gj_update(double* M, int np, int kb, const double* __restrict__ P,
                                                  const double* __restrict__ Cbuf) {
     int nbk = np / GJ_B;
@@ -799,7 +778,7 @@ __global__ void __launch_bounds__(256) gj_update(double* M, int np, int kb, cons
     }
     const double* X = Cbuf + (int64_t)ib * GJ_B * GJ_B;
     if (jb == kb) {
-        d4v acc = tile_mm<MF>(X, GJ_B, P, GJ_B, qr, qc);
+        d4v acc = mfma_tile(X, GJ_B, P, GJ_B, qr, qc);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             int r, c;
@@ -808,7 +787,7 @@ __global__ void __launch_bounds__(256) gj_update(double* M, int np, int kb, cons
         }
     } else {
         const double* Y = M + (int64_t)kb * GJ_B * np + jb * GJ_B;
-        d4v acc = tile_mm<MF>(X, GJ_B, Y, np, qr, qc);
+        d4v acc = mfma_tile(X, GJ_B, Y, np, qr, qc);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             int r, c;
@@ -822,16 +801,10 @@ __global__ void __launch_bounds__(256) gj_update(double* M, int np, int kb, cons
 // P: 32x32 scratch, C: np x 32 scratch, bad: set to 1 on a zero pivot.
 void gj_invert(hipStream_t st, double* M, int np, double* P, double* C, int* bad) {
     int nbk = np / GJ_B;
-    static const bool plain = getenv("DPSIM_GJ_PLAIN") != nullptr;
     for (int kb = 0; kb < nbk; ++kb) {
         gj_diag<<<1, 64, 0, st>>>(M, np, kb, P, bad);
-        if (plain) {
-            gj_row<false><<<2 * nbk, 256, 0, st>>>(M, np, kb, P, C);
-            gj_update<false><<<nbk * nbk, 256, 0, st>>>(M, np, kb, P, C);
-        } else {
-            gj_row<true><<<2 * nbk, 256, 0, st>>>(M, np, kb, P, C);
-            gj_update<true><<<nbk * nbk, 256, 0, st>>>(M, np, kb, P, C);
-        }
+        gj_row<<<2 * nbk, 256, 0, st>>>(M, np, kb, P, C);
+        gj_update<<<nbk * nbk, 256, 0, st>>>(M, np, kb, P, C);
     }
     DP_LAUNCH_CHECK();
 }
