@@ -8,7 +8,7 @@ of 1e-6.  The Jacobian is taken at the third Newton iterate of the first
 injector) and is re-assembled and set up from scratch in every step.  The headline value uses the FP32 preconditioner under the FP64 Krylov
 loop; the plain FP64 form is measured in the same run.
 
-Prints one JSON line.  --gpus N with N > 1 exits: this build runs on one GPU.
+Prints one JSON line.  --gpus N with N > 1 exits: the library runs on one GPU.
 """
 import argparse
 import json
@@ -313,8 +313,8 @@ def main():
     ap.add_argument("--precision", default="fp32", help="with --example: preconditioner precision")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the solve would shard)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (a sharded solve "
+              "would split the grid into slabs along y, one per GPU)", file=sys.stderr)
         sys.exit(2)
     import torch
 
