@@ -207,6 +207,23 @@ def _run_both(m, steps, **opts):
     return out
 
 
+@pytest.mark.parametrize("name", ["single_cell", "two_cells"])
+def test_degenerate_grids_match_oracle(name):
+    """The smallest systems the method has: one cell without wells (4
+    unknowns; one-level hierarchy of one row, no second ILU colour), relaxing
+    to matrix-fracture equilibrium over a long step, and two cells holding one
+    injector and one producer."""
+    m = synth.model_single_cell() if name == "single_cell" else synth.model_tiny(2, 1, 1, seed=8)
+    for (pg, sg, bg), (po, so, bo), info, rep in _run_both(m, 1):
+        assert rel_max(pg, po) <= 1e-9
+        assert np.abs(sg - so).max() <= 1e-9
+        if bo.size:
+            assert rel_max(bg, bo) <= 1e-9
+    if name == "single_cell":
+        # equilibrium: both nodes at one pressure
+        assert abs(pg[0] - pg[1]) <= 1e-6 * abs(pg[0])
+
+
 @pytest.mark.parametrize("name", ["c0", "tiny_grav", "column"])
 def test_timesteps_match_oracle(name):
     m = MODELS[name]()
