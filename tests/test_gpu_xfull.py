@@ -7,8 +7,10 @@ entry (residual, Jacobian, decoupled system, the solution's true residual);
 the oracle's own AMG hierarchy is built at full size and compared level by
 level; elsewhere properties that hold at any size are checked (the block
 ILU(0) identity (LU)_ij = A_ij on the pattern on sampled rows, the Galerkin
-identity A_1 = P^T A_0 P, and the PMIS cover rule).  The file runs
-after the other GPU tests (its name sorts last among them)."""
+identity A_1 = P^T A_0 P, and the PMIS cover rule).  One more test takes the
+first Jacobian of bench.py's default workload, the converged state after the
+first step of the run.  The file runs after the other GPU tests (its name sorts
+last among them)."""
 import numpy as np
 import pytest
 import scipy.sparse as sp
@@ -194,3 +196,64 @@ def test_full_amg_hierarchy_matches_oracle(full):
     hasc = np.zeros(A0.shape[0], dtype=bool)
     hasc[r[sm & (cf[c] == 1)]] = True
     assert np.all(hasc[(cf == -1) & (nst > 0)])
+
+
+def _residual_err(m, geo, x, acc_old, dt, Rg, R):
+    """max over rows of |Rg - R| over the size of the terms the row sums.  At a
+    converged state the terms cancel, so the row's own value is no scale for
+    rounding.  Node rows: (|M_a(x)| + |M_a^n|)/dt + |the flux, transfer and
+    well part|.  Well rows: |R| + rho_ref |target| for rate and oil-rate rows,
+    |R| + |target| for BHP rows."""
+    n = geo.n
+    scale = np.zeros_like(R)
+    for a, acc_new in enumerate(oph.accumulation(geo, x)):
+        rows = slice(a, 4 * n, 2)
+        dm = (acc_new - acc_old[a]) / dt
+        scale[rows] = (np.abs(acc_new) + np.abs(acc_old[a])) / dt + np.abs(R[rows] - dm)
+    for w, wl in enumerate(m["wells"]):
+        r = 4 * n + 2 * w
+        rho = {"rate": m["rho_w_ref"], "orate": m["rho_o_ref"]}.get(wl["control"], 1.0)
+        scale[r] = abs(R[r]) + rho * abs(wl["target"])
+        scale[r + 1] = max(abs(R[r + 1]), 1.0)  # the dummy row
+    return (np.abs(Rg - R) / scale).max()
+
+
+def test_full_run_state_matches_oracle(full):
+    """The first Jacobian of bench.py's default workload (the Jacobian set of a
+    run): the converged state after the first 10-day step, with the initial
+    state as the old time level and the 10-day step length.  Residual and
+    Jacobian against the oracle's at 1e-12 of each row's scale (for the
+    residual, the size of the terms it sums), and the GPU
+    solution's decoupled residual recomputed by the oracle within 1.001e-6."""
+    from paper_1808_04338_amd import Sim
+
+    m, geo = full["m"], full["geo"]
+    dt = m["schedule"][0]
+    run = Sim(m, precision="fp32")
+    old = run.get_state()
+    run.timestep(dt)
+    cur = run.get_state()
+    run.close()
+    sim = Sim(m, precision="fp32", lin_rtol=1e-6)
+    try:
+        sim.set_state(*old)
+        sim.mark_old()
+        sim.set_state(*cur)
+        sim.assemble(dt)
+        sim.setup()
+        its, rel_g = sim.solve(1e-6, 300, allow_noconv=True)
+        x_old, x = oph.pack_state(*old), oph.pack_state(*cur)
+        acc = oph.accumulation(geo, x_old)
+        R = oph.residual(geo, x, acc, dt, controls(m))
+        J = oph.jacobian(geo, x, dt, controls(m)).tocsr()
+        Jg, Rg = sim.export_system(0)
+        assert _residual_err(m, geo, x, acc, dt, Rg, R) <= 1e-12
+        assert _row_err(Jg, J) <= 1e-12
+        indptr, indices, data = oph.to_bsr(geo, J)
+        dh, bh = ocpr.decouple(2 * geo.n, indptr, indices, data, -R)
+        Ah = oph.bsr_to_csr(indptr, indices, dh)
+        y = sim.get_correction()
+        assert rel_g <= 1e-6 and its > 10  # harder than the first-step Jacobian
+        assert np.linalg.norm(bh - Ah @ y) / np.linalg.norm(bh) <= 1.001e-6
+    finally:
+        sim.close()
