@@ -26,8 +26,8 @@ constexpr int ST_F = -1;
 // fracture diagonal: a_ff - a_fm (1/a_mm) a_mf.
 // ---------------------------------------------------------------------------
 __global__ void extract_ap_kernel(BMat<double> A, const int* __restrict__ rowptr,
-                                  const int* __restrict__ src, const int* __restrict__ fperf,
-                                  const int* __restrict__ fcell, int n, int nr, double* val) {
+                                  const int* __restrict__ src, const int* __restrict__ fperf, int n,
+                                  int nr, double* val) {
     int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nr) return;
     for (int e = rowptr[r]; e < rowptr[r + 1]; ++e) {
@@ -38,8 +38,7 @@ __global__ void extract_ap_kernel(BMat<double> A, const int* __restrict__ rowptr
             if (code < 6) {
                 v = A.f0[(int64_t)code * n + q].x;
             } else if (code == 7) {
-                int c = fcell[q];
-                v = A.d0[n + q].x - A.f0[(int64_t)6 * n + q].x * (1.0 / A.d0[c].x) * A.m0[c].x;
+                v = A.d0[n + q].x - A.f0[(int64_t)6 * n + q].x * (1.0 / A.d0[q].x) * A.m0[q].x;
             } else {
                 v = A.fw0[fperf[q]].x;
             }
@@ -54,7 +53,7 @@ void amg_extract_level0(dp_sim* s) {
     Topo& t = s->topo;
     int nr = t.n + t.nw;
     extract_ap_kernel<<<ceil_div(nr, 256), 256, 0, s->stream>>>(s->A, s->Ap0.rowptr, s->ap_src, t.fperf,
-                                                               t.fcell, t.n, nr, s->Ap0.val);
+                                                               t.n, nr, s->Ap0.val);
     DP_LAUNCH_CHECK();
 }
 

@@ -19,19 +19,20 @@ struct GeoIn {
 
 // Transmissibility of each fracture slot (harmonic two-point form
 // T = 2 A k_lo k_hi / (L (k_lo + k_hi))), transfer coefficient sigma km V,
-// pore volumes V phi and depths.
-__global__ void geometry_kernel(GeoIn g, const int* __restrict__ fcol, const int* __restrict__ fcell,
+// pore volumes V phi and depths.  The input fields are in grid-cell order
+// (cell[q] is the cell of node pair q); the outputs are indexed by q.
+__global__ void geometry_kernel(GeoIn g, const int* __restrict__ fcol, const int* __restrict__ cell,
                                 const unsigned char* __restrict__ fmask, int n, double* tface,
                                 double* tmf, double* pvf, double* pvm, double* depth) {
     int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= n) return;
-    int c = fcell[q];
+    int c = cell[q];
     double vol = g.dx * g.dy * g.dz;
     int k = c / (g.nx * g.ny);
     for (int s = 0; s < 6; ++s) {
         double t = 0.0;
         if (fmask[q] & (1u << s)) {
-            int d = fcell[fcol[s * n + q] - n];
+            int d = cell[fcol[s * n + q] - n];
             int lo = (s & 1) ? c : d;
             int hi = (s & 1) ? d : c;
             const double* kk = s < 2 ? g.kx : (s < 4 ? g.ky : g.kz);
@@ -41,10 +42,10 @@ __global__ void geometry_kernel(GeoIn g, const int* __restrict__ fcol, const int
         }
         tface[s * n + q] = t;
     }
-    tmf[c] = g.sigma * g.km[c] * vol;
-    pvf[c] = vol * g.phi_f[c];
-    pvm[c] = vol * g.phi_m[c];
-    depth[c] = g.top_depth + k * g.dz;
+    tmf[q] = g.sigma * g.km[c] * vol;
+    pvf[q] = vol * g.phi_f[c];
+    pvm[q] = vol * g.phi_m[c];
+    depth[q] = g.top_depth + k * g.dz;
 }
 
 // Peaceman well index of every perforation: W = 2 pi sqrt(kx ky) dz / (ln(r_e/r_w) + s),
@@ -77,7 +78,7 @@ void launch_geometry(dp_sim* s, const double* kx, const double* ky, const double
     Topo& t = s->topo;
     GeoIn g{kx, ky, kz, km, phi_f, phi_m, s->desc.dx, s->desc.dy, s->desc.dz,
             s->desc.top_depth, s->desc.sigma, t.nx, t.ny, t.n};
-    geometry_kernel<<<ceil_div(t.n, 256), 256, 0, s->stream>>>(g, t.fcol, t.fcell, t.fmask, t.n,
+    geometry_kernel<<<ceil_div(t.n, 256), 256, 0, s->stream>>>(g, t.fcol, t.cell, t.fmask, t.n,
                                                                t.tface, t.tmf, t.pvf, t.pvm, t.depth);
     DP_LAUNCH_CHECK();
     if (t.nperf > 0) {
@@ -113,11 +114,10 @@ Phys make_phys(const dp_sim* s) {
 // Accumulation M = V phi(p) (S rho) per node, at the start of a step
 // ---------------------------------------------------------------------------
 __global__ void accumulation_kernel(Phys P, const d2* __restrict__ x, const double* __restrict__ pvf,
-                                    const double* __restrict__ pvm, const int* __restrict__ fcell,
-                                    int n, d2* acc) {
+                                    const double* __restrict__ pvm, int n, d2* acc) {
     int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= 2 * n) return;
-    double pv = r < n ? pvm[r] : pvf[fcell[r - n]];
+    double pv = r < n ? pvm[r] : pvf[r - n];
     d2 v = x[r];
     double rho_o = P.rho_ref[0] * exp(P.c[0] * (v.x - P.p_ref));
     double rho_w = P.rho_ref[1] * exp(P.c[1] * (v.x - P.p_ref));
@@ -128,7 +128,7 @@ __global__ void accumulation_kernel(Phys P, const d2* __restrict__ x, const doub
 void launch_accumulation(dp_sim* s, const d2* x, d2* acc) {
     Topo& t = s->topo;
     accumulation_kernel<<<ceil_div(2 * t.n, 256), 256, 0, s->stream>>>(make_phys(s), x, t.pvf, t.pvm,
-                                                                       t.fcell, t.n, acc);
+                                                                       t.n, acc);
     DP_LAUNCH_CHECK();
 }
 
@@ -142,7 +142,6 @@ struct AsmArgs {
     const d2* acc_old;
     const int* fcol;
     const unsigned char* fmask;
-    const int* fcell;
     const int* fperf;
     const int* perf_q;
     const int* perf_well;
@@ -176,11 +175,11 @@ __device__ inline void accum_row(const Phys& P, double pv, double dt, double p, 
     D[1][1] = pvp * pr.rho[1] / dt;
 }
 
-// Matrix row of cell c: accumulation minus the transfer from its fracture node.
-__device__ void assemble_matrix_row(const AsmArgs& a, const int* frow, int c) {
+// Matrix row c: accumulation minus the transfer from its fracture node n + c.
+__device__ void assemble_matrix_row(const AsmArgs& a, int c) {
     const Phys& P = a.P;
     int n = a.n;
-    int fpos = n + frow[c];
+    int fpos = n + c;
     d2 xm = a.x[c];
     d2 xf = a.x[fpos];
     Props pm = props(P, xm.x, xm.y);
@@ -209,7 +208,7 @@ __device__ void assemble_matrix_row(const AsmArgs& a, const int* frow, int c) {
 __device__ void assemble_fracture_row(const AsmArgs& a, int q) {
     const Phys& P = a.P;
     int n = a.n;
-    int c = a.fcell[q];
+    int c = q;  // its matrix node
     int pos = n + q;
     d2 xf = a.x[pos];
     Props pf = props(P, xf.x, xf.y);
@@ -346,12 +345,11 @@ __device__ void assemble_well_row(const AsmArgs& a, int w) {
     }
 }
 
-__global__ void __launch_bounds__(256) assemble_kernel(AsmArgs a, const int* __restrict__ frow,
-                                                       int blocks_m, int blocks_f) {
+__global__ void __launch_bounds__(256) assemble_kernel(AsmArgs a, int blocks_m, int blocks_f) {
     int b = blockIdx.x;
     if (b < blocks_m) {
         int c = b * blockDim.x + threadIdx.x;
-        if (c < a.n) assemble_matrix_row(a, frow, c);
+        if (c < a.n) assemble_matrix_row(a, c);
     } else if (b < blocks_m + blocks_f) {
         int q = (b - blocks_m) * blockDim.x + threadIdx.x;
         if (q < a.n) assemble_fracture_row(a, q);
@@ -369,7 +367,6 @@ void launch_assemble(dp_sim* s, double dt) {
     a.acc_old = s->acc_old;
     a.fcol = t.fcol;
     a.fmask = t.fmask;
-    a.fcell = t.fcell;
     a.fperf = t.fperf;
     a.perf_q = t.perf_q;
     a.perf_well = t.perf_well;
@@ -387,7 +384,7 @@ void launch_assemble(dp_sim* s, double dt) {
     a.J = s->J;
     a.R = s->res;
     int bm = ceil_div(t.n, 256);
-    assemble_kernel<<<2 * bm + t.nw, 256, 0, s->stream>>>(a, t.frow, bm, bm);
+    assemble_kernel<<<2 * bm + t.nw, 256, 0, s->stream>>>(a, bm, bm);
     DP_LAUNCH_CHECK();
 }
 
@@ -402,14 +399,13 @@ void launch_assemble(dp_sim* s, double dt) {
 constexpr int RN_BLOCKS = 1024;
 
 __global__ void resnorm_kernel(const d2* __restrict__ R, const double* __restrict__ pvf,
-                               const double* __restrict__ pvm, const int* __restrict__ fcell,
-                               const double* __restrict__ well_scale, int n, int nw, double dt,
+                               const double* __restrict__ pvm, const double* __restrict__ well_scale, int n, int nw, double dt,
                                double rho_o, double rho_w, double* part) {
     __shared__ double sh[3][256 / WAVE];
     double v = 0.0, so = 0.0, sw = 0.0;
     for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < 2 * n + nw; r += gridDim.x * blockDim.x) {
         if (r < 2 * n) {
-            double pv = r < n ? pvm[r] : pvf[fcell[r - n]];
+            double pv = r < n ? pvm[r] : pvf[r - n];
             d2 x = R[r];
             double a = fabs(x.x) * dt / (rho_o * pv);
             double b = fabs(x.y) * dt / (rho_w * pv);
@@ -479,7 +475,7 @@ ResNorm residual_norm(dp_sim* s, double dt) {
     Topo& t = s->topo;
     int nblk = std::min(ceil_div(2 * t.n + t.nw, 256), RN_BLOCKS);
     if (3 * nblk > 32 * s->red_blocks) fail(DP_E_INVALID, "reduction buffer too small");
-    resnorm_kernel<<<nblk, 256, 0, s->stream>>>(s->res, t.pvf, t.pvm, t.fcell, t.well_scale, t.n,
+    resnorm_kernel<<<nblk, 256, 0, s->stream>>>(s->res, t.pvf, t.pvm, t.well_scale, t.n,
                                                 t.nw, dt, s->rho_o_ref, s->rho_w_ref, s->red_part);
     resnorm_final<<<1, 256, 0, s->stream>>>(s->red_part, nblk, s->red_out);
     DP_LAUNCH_CHECK();

@@ -150,6 +150,18 @@ __device__ inline void stb(V2<T>* r0, V2<T>* r1, int64_t i, const Blk<T>& b) {
 // ---------------------------------------------------------------------------
 constexpr int WAVE = 64;
 
+// Workgroups go to the eight XCDs round-robin (workgroup b runs on XCD b mod
+// 8), and each XCD has its own L2.  xcd_block renumbers the blocks of a grid of
+// nblk so that every XCD sweeps one contiguous stretch of the logical blocks:
+// rows that gather from nearby rows (a grid layer up or down, a few dozen
+// workgroups away) then find them in their own L2.  A bijection on [0, nblk).
+__device__ inline int xcd_block(int b, int nblk) {
+    constexpr int NXCD = 8;
+    int q = nblk / NXCD, r = nblk % NXCD;
+    int x = b % NXCD, k = b / NXCD;
+    return x < r ? x * (q + 1) + k : r * (q + 1) + (x - r) * q + k;
+}
+
 __device__ inline double wave_sum(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);

@@ -25,8 +25,6 @@ struct DecArgs {
     d2* b;
     const unsigned char* fmask;
     const int* fcol;
-    const int* fcell;
-    const int* frow;
     const int* fperf;
     const int* well_ptr;
     int n, nw;
@@ -71,7 +69,7 @@ __global__ void __launch_bounds__(256) decouple_kernel(DecArgs a, int bm, int bf
             // that couples another row to this node
             double c01 = d0.y, c11 = d1.y;
             if (!frac) {
-                int64_t e = (int64_t)6 * n + a.frow[pos];  // matrix slot of its fracture row
+                int64_t e = (int64_t)6 * n + pos;  // matrix slot of its fracture row
                 c01 += a.J.f0[e].y;
                 c11 += a.J.f1[e].y;
             } else {
@@ -83,9 +81,8 @@ __global__ void __launch_bounds__(256) decouple_kernel(DecArgs a, int bm, int bf
                     c01 += a.J.f0[e].y;
                     c11 += a.J.f1[e].y;
                 }
-                int c = a.fcell[pos];
-                c01 += a.J.m0[c].y;
-                c11 += a.J.m1[c].y;
+                c01 += a.J.m0[pos].y;  // its matrix node
+                c11 += a.J.m1[pos].y;
                 if (p >= 0) {
                     c01 += a.J.wf0[p].y;
                     c11 += a.J.wf1[p].y;
@@ -136,8 +133,6 @@ void launch_decouple(dp_sim* s) {
     a.b = s->rhs;
     a.fmask = t.fmask;
     a.fcol = t.fcol;
-    a.fcell = t.fcell;
-    a.frow = t.frow;
     a.fperf = t.fperf;
     a.well_ptr = t.well_ptr;
     a.n = t.n;
@@ -168,8 +163,6 @@ struct SpArgs {
     T* yp;          // MODE_RESP
     V2<T>* x2;      // MODE_PROL
     const int* fcol;
-    const int* fcell;
-    const int* frow;
     const int* fperf;
     const int* perf_q;
     const int* perf_well;
@@ -182,7 +175,7 @@ __device__ inline V2<T> xval(const SpArgs<T>& a, int pos) {
     V2<T> v = a.x[pos];
     if (MODE == MODE_PROL) {
         if (pos < a.n) {
-            T ef = a.e[a.frow[pos]];
+            T ef = a.e[pos];
             v.x += (a.rpm[pos] - a.A.m0[pos].x * ef) / a.A.d0[pos].x;
         } else {
             v.x += a.e[pos - a.n];
@@ -228,7 +221,7 @@ __global__ void __launch_bounds__(256) spmv_kernel(SpArgs<T> a, int bm, int bf) 
         T y0 = 0, y1 = 0;
         V2<T> xs = xval<T, MODE>(a, c);
         acc_blk<T, MODE>(a.A.d0, a.A.d1, c, xs, y0, y1);
-        acc_blk<T, MODE>(a.A.m0, a.A.m1, c, xval<T, MODE>(a, n + a.frow[c]), y0, y1);
+        acc_blk<T, MODE>(a.A.m0, a.A.m1, c, xval<T, MODE>(a, n + c), y0, y1);
         sp_store<T, MODE>(a, c, y0, y1, xs);
     } else if (b < bm + bf) {
         int q = (b - bm) * blockDim.x + threadIdx.x;
@@ -240,7 +233,7 @@ __global__ void __launch_bounds__(256) spmv_kernel(SpArgs<T> a, int bm, int bf) 
 #pragma unroll
         for (int s = 0; s < 6; ++s)
             acc_blk<T, MODE>(a.A.f0, a.A.f1, (int64_t)s * n + q, xval<T, MODE>(a, a.fcol[s * n + q]), y0, y1);
-        acc_blk<T, MODE>(a.A.f0, a.A.f1, (int64_t)6 * n + q, xval<T, MODE>(a, a.fcell[q]), y0, y1);
+        acc_blk<T, MODE>(a.A.f0, a.A.f1, (int64_t)6 * n + q, xval<T, MODE>(a, q), y0, y1);
         int p = a.fperf[q];
         if (p >= 0) acc_blk<T, MODE>(a.A.fw0, a.A.fw1, p, xval<T, MODE>(a, 2 * n + a.perf_well[p]), y0, y1);
         sp_store<T, MODE>(a, row, y0, y1, xs);
@@ -284,7 +277,7 @@ __global__ void __launch_bounds__(256) presid_red_kernel(SpArgs<T> a, int bf, T*
         int q = b * blockDim.x + threadIdx.x;
         if (q >= n) return;
         int row = n + q;
-        int c = a.fcell[q];
+        int c = q;  // the matrix node of fracture row q
         T y0 = 0, dummy = 0;
         acc_blk<T, MODE_RESP>(a.A.d0, a.A.d1, row, a.x[row], y0, dummy);
 #pragma unroll
@@ -325,8 +318,6 @@ static SpArgs<T> sp_args(dp_sim* s, const BMat<T>& A) {
     SpArgs<T> a{};
     a.A = A;
     a.fcol = t.fcol;
-    a.fcell = t.fcell;
-    a.frow = t.frow;
     a.fperf = t.fperf;
     a.perf_q = t.perf_q;
     a.perf_well = t.perf_well;
@@ -417,7 +408,6 @@ struct IluArgs {
     ILUF<T> F;
     const int* fcol;
     const unsigned char* fmask;
-    const int* fcell;
     const int* fperf;
     const int* perf_q;
     const int* perf_well;
@@ -431,7 +421,7 @@ __global__ void ilu_red_kernel(IluArgs<T> a) {
     int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= a.nred) return;
     int n = a.n;
-    int c = a.fcell[q];
+    int c = q;  // the matrix node of fracture row q
     Blk<T> um_inv = binv(ldb(a.A.d0, a.A.d1, c));
     stb(a.F.ui0, a.F.ui1, c, um_inv);
     Blk<T> l = bmm(ldb(a.A.f0, a.A.f1, (int64_t)6 * n + q), um_inv);
@@ -448,7 +438,7 @@ __global__ void ilu_black_kernel(IluArgs<T> a) {
     int q = a.nred + blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= a.n) return;
     int n = a.n;
-    int c = a.fcell[q];
+    int c = q;  // the matrix node of fracture row q
     Blk<T> um_inv = binv(ldb(a.A.d0, a.A.d1, c));
     stb(a.F.ui0, a.F.ui1, c, um_inv);
     Blk<T> l6 = bmm(ldb(a.A.f0, a.A.f1, (int64_t)6 * n + q), um_inv);
@@ -543,7 +533,6 @@ static IluArgs<T> ilu_args(dp_sim* s) {
     a.F = ilu_of<T>(s);
     a.fcol = t.fcol;
     a.fmask = t.fmask;
-    a.fcell = t.fcell;
     a.fperf = t.fperf;
     a.perf_q = t.perf_q;
     a.perf_well = t.perf_well;
@@ -586,20 +575,20 @@ struct IluSolveArgs {
 
 template <class T>
 __global__ void ilus_red_fwd(IluSolveArgs<T> a) {
-    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    int q = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (q >= a.f.nred) return;
     int n = a.f.n;
-    int c = a.f.fcell[q];
+    int c = q;  // the matrix node of fracture row q
     V2<T> y = vsub(a.r[n + q], bmv(ldb(a.f.F.l0, a.f.F.l1, (int64_t)6 * n + q), a.r[c]));
     a.z[n + q] = y;
 }
 
 template <class T>
 __global__ void ilus_black(IluSolveArgs<T> a) {
-    int q = a.f.nred + blockIdx.x * blockDim.x + threadIdx.x;
+    int q = a.f.nred + xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (q >= a.f.n) return;
     int n = a.f.n;
-    int c = a.f.fcell[q];
+    int c = q;  // the matrix node of fracture row q
     V2<T> rm = a.r[c];
     V2<T> y = vsub(a.r[n + q], bmv(ldb(a.f.F.l0, a.f.F.l1, (int64_t)6 * n + q), rm));
     unsigned mask = a.f.fmask[q];
@@ -652,7 +641,7 @@ __global__ void ilus_well(IluSolveArgs<T> a) {
     for (int p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
         int q = a.f.perf_q[p];
         if (q < a.f.nred) continue;
-        int c = a.f.fcell[q];
+        int c = q;  // the matrix node of fracture row q
         V2<T> y = vsub(a.z[n + q], bmv(ldb(a.f.F.ubw0, a.f.F.ubw1, p), zw));
         V2<T> zb = bmv(ldb(a.f.F.ui0, a.f.F.ui1, n + q), y);
         a.z[n + q] = zb;
@@ -662,10 +651,10 @@ __global__ void ilus_well(IluSolveArgs<T> a) {
 
 template <class T>
 __global__ void ilus_red_bwd(IluSolveArgs<T> a) {
-    int q = blockIdx.x * blockDim.x + threadIdx.x;
+    int q = xcd_block(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
     if (q >= a.f.nred) return;
     int n = a.f.n;
-    int c = a.f.fcell[q];
+    int c = q;  // the matrix node of fracture row q
     V2<T> y = a.z[n + q];
     unsigned mask = a.f.fmask[q];
 #pragma unroll

@@ -1,14 +1,18 @@
 // The simulator handle and the device data layout.
 //
 // Internal block order ("elimination order"), used by every device array:
-//   positions 0 .. n-1        matrix node of cell c (position = c)
 //   positions n .. 2n-1       fracture nodes: first the cells with i+j+k even
-//                             (by cell index), then those with i+j+k odd
+//                             (by cell index), then those with i+j+k odd;
+//                             fracture row q = position n+q
+//   positions 0 .. n-1        matrix nodes, in the same order: the matrix node
+//                             of fracture row q's cell sits at position q
 //   positions 2n .. 2n+nw-1   wells
-// A fracture row q (0..n-1, position n+q) has 7 coupling slots: 0..5 the
-// fracture neighbours in -x,+x,-y,+y,-z,+z (slot absent at the boundary: its
-// column points at the row itself and its block is zero) and 6 the matrix node
-// of the same cell.  A matrix row c has one coupling: the fracture node of c.
+// Node pair q (the two nodes of one cell) thus shares index q in every
+// per-cell array, and a sweep over the rows of one colour reads them at unit
+// stride.  A fracture row q has 7 coupling slots: 0..5 the fracture
+// neighbours in -x,+x,-y,+y,-z,+z (slot absent at the boundary: its column
+// points at the row itself and its block is zero) and 6 the matrix node q.
+// Matrix row q has one coupling: fracture row q.
 // Perforation p couples fracture row perf_q[p] and well perf_well[p] in both
 // directions.  Blocks are stored as two planes of 2-vectors (row 0, row 1) so
 // that kernels that need only the pressure row read half the bytes.
@@ -26,8 +30,7 @@ struct Topo {
     // device
     int* fcol = nullptr;          // [6*n] slot-major: neighbour position
     unsigned char* fmask = nullptr;  // [n] bit s: slot s has a face
-    int* fcell = nullptr;         // [n] cell of fracture row q
-    int* frow = nullptr;          // [n] fracture row q of cell c
+    int* cell = nullptr;          // [n] grid cell of node pair q (geometry inputs only)
     int* fperf = nullptr;         // [n] perforation of fracture row q or -1
     int* perf_q = nullptr;        // [nperf]
     int* perf_well = nullptr;     // [nperf]
@@ -37,13 +40,13 @@ struct Topo {
     double* well_target = nullptr;  // [nw] rate (m^3/s) or BHP (Pa) of the current control
     double* well_scale = nullptr;   // [nw] 1/scale of the control row in the convergence norm
     double* tface = nullptr;      // [6*n] transmissibility per slot (0 when absent)
-    double* tmf = nullptr;        // [n] sigma km V
-    double* pvf = nullptr;        // [n] V phi_f
-    double* pvm = nullptr;        // [n] V phi_m
-    double* depth = nullptr;      // [n] cell-centre depth
+    double* tmf = nullptr;        // [n] sigma km V of node pair q
+    double* pvf = nullptr;        // [n] V phi_f of node pair q
+    double* pvm = nullptr;        // [n] V phi_m of node pair q
+    double* depth = nullptr;      // [n] cell-centre depth of node pair q
     double* wi = nullptr;         // [nperf]
     // host mirrors
-    std::vector<int> h_fcol, h_fcell, h_frow_of_cell, h_fperf, h_perf_q, h_perf_well, h_well_ptr;
+    std::vector<int> h_fcol, h_fcell, h_fperf, h_perf_q, h_perf_well, h_well_ptr;  // h_fcell: grid cell of q
     std::vector<unsigned char> h_fmask;
 };
 

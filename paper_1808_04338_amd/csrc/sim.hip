@@ -208,8 +208,7 @@ static Layout layout(dp_sim* s, Arena& a, const HostTopo& h) {
     Topo& t = s->topo;
     t.fcol = a.get<int>((int64_t)6 * n, "topology");
     t.fmask = a.get<unsigned char>(n, "topology");
-    t.fcell = a.get<int>(n, "topology");
-    t.frow = a.get<int>(n, "topology");
+    t.cell = a.get<int>(n, "topology");
     t.fperf = a.get<int>(n, "topology");
     t.perf_q = a.get<int>(nperf, "topology");
     t.perf_well = a.get<int>(nperf, "topology");
@@ -341,7 +340,7 @@ static void set_controls(dp_sim* s, const std::vector<int>& ctrl) {
 // canonical block index of each elimination position
 static int canon_of_pos(const dp_sim* s, int pos) {
     const Topo& t = s->topo;
-    if (pos < t.n) return 2 * pos + 1;
+    if (pos < t.n) return 2 * t.h_fcell[pos] + 1;
     if (pos < 2 * t.n) return 2 * t.h_fcell[pos - t.n];
     return pos;
 }
@@ -503,7 +502,7 @@ constexpr int MS_BLOCKS = 512;
 
 __global__ void mass_sums_kernel(Phys P, const d2* __restrict__ x, const d2* __restrict__ acc_old,
                                  const double* __restrict__ pvf, const double* __restrict__ pvm,
-                                 const int* __restrict__ fcell, const int* __restrict__ perf_q,
+                                 const int* __restrict__ perf_q,
                                  const int* __restrict__ perf_well, const int* __restrict__ well_kind,
                                  const double* __restrict__ wi, int n, int nperf, double* part) {
     __shared__ double sh[6][256 / WAVE];
@@ -513,7 +512,7 @@ __global__ void mass_sums_kernel(Phys P, const d2* __restrict__ x, const d2* __r
         d2 o = acc_old[r];
         v[0] += o.x;
         v[1] += o.y;
-        double pv = r < n ? pvm[r] : pvf[fcell[r - n]];
+        double pv = r < n ? pvm[r] : pvf[r - n];
         d2 xx = x[r];
         double rho_o = P.rho_ref[0] * exp(P.c[0] * (xx.x - P.p_ref));
         double rho_w = P.rho_ref[1] * exp(P.c[1] * (xx.x - P.p_ref));
@@ -554,9 +553,8 @@ __global__ void mass_sums_final(const double* __restrict__ part, int nblk, doubl
 static void mass_sums(dp_sim* s, double out[6]) {
     Topo& t = s->topo;
     int nblk = (int)std::min<int64_t>(MS_BLOCKS, std::max<int64_t>(1, ceil_div(2 * (int64_t)t.n, 256)));
-    mass_sums_kernel<<<nblk, 256, 0, s->stream>>>(make_phys(s), s->x, s->acc_old, t.pvf, t.pvm, t.fcell,
-                                                  t.perf_q, t.perf_well, t.well_kind, t.wi, t.n, t.nperf,
-                                                  s->red_part);
+    mass_sums_kernel<<<nblk, 256, 0, s->stream>>>(make_phys(s), s->x, s->acc_old, t.pvf, t.pvm, t.perf_q,
+                                                  t.perf_well, t.well_kind, t.wi, t.n, t.nperf, s->red_part);
     DP_LAUNCH_CHECK();
     mass_sums_final<<<1, 64, 0, s->stream>>>(s->red_part, nblk, s->red_out + 128);
     DP_LAUNCH_CHECK();
@@ -763,7 +761,7 @@ double kernel_bytes(dp_sim* s, int kernel) {
     double n = t.n, nb = t.nb, np = t.nperf;
     double es = s->fp32 ? 4.0 : 8.0;
     double blocks = nb + 7 * n + n + 2 * np;     // stored blocks of the matrix
-    double idx = 4.0 * (6 * n + 3 * n + 3 * np) + n;  // fcol, fcell, frow, fperf, perforations, fmask
+    double idx = 4.0 * (6 * n + n + 3 * np) + n;  // fcol, fperf, perforations, fmask
     double vec = 16.0 * nb;
     if (kernel == 0) return blocks * 32.0 + idx + 2 * vec;
     if (kernel == 1) {
@@ -877,7 +875,6 @@ dp_status sim_create(const dp_sim_desc* desc, const double* p0, const double* sw
         t.nred = h.nred;
         t.h_fcol = h.fcol;
         t.h_fcell = h.fcell;
-        t.h_frow_of_cell = h.frow;
         t.h_fperf = h.fperf;
         t.h_perf_q = h.perf_q;
         t.h_perf_well = h.perf_well;
@@ -903,8 +900,7 @@ dp_status sim_create(const dp_sim_desc* desc, const double* p0, const double* sw
         int n = h.n;
         up(t.fcol, h.fcol.data(), sizeof(int) * h.fcol.size());
         up(t.fmask, h.fmask.data(), h.fmask.size());
-        up(t.fcell, h.fcell.data(), sizeof(int) * n);
-        up(t.frow, h.frow.data(), sizeof(int) * n);
+        up(t.cell, h.fcell.data(), sizeof(int) * n);
         up(t.fperf, h.fperf.data(), sizeof(int) * n);
         up(t.perf_q, h.perf_q.data(), sizeof(int) * h.nperf);
         up(t.perf_well, h.perf_well.data(), sizeof(int) * h.nperf);
@@ -1185,13 +1181,13 @@ static void for_each_block(dp_sim* s, const BMat<double>& M, F f) {
         int br = canon_of_pos(s, pos);
         f(br, br, mkb(d0[pos], d1[pos]));
         if (pos < n) {
-            f(br, canon_of_pos(s, n + t.h_frow_of_cell[pos]), mkb(m0[pos], m1[pos]));
+            f(br, canon_of_pos(s, n + pos), mkb(m0[pos], m1[pos]));
         } else if (pos < 2 * n) {
             int q = pos - n;
             for (int sl = 0; sl < 6; ++sl)
                 if (t.h_fmask[q] & (1u << sl))
                     f(br, canon_of_pos(s, t.h_fcol[(size_t)sl * n + q]), mkb(f0[(size_t)sl * n + q], f1[(size_t)sl * n + q]));
-            f(br, canon_of_pos(s, t.h_fcell[q]), mkb(f0[(size_t)6 * n + q], f1[(size_t)6 * n + q]));
+            f(br, canon_of_pos(s, q), mkb(f0[(size_t)6 * n + q], f1[(size_t)6 * n + q]));
             int p = t.h_fperf[q];
             if (p >= 0) f(br, 2 * n + t.h_perf_well[p], mkb(fw0[p], fw1[p]));
         } else {
@@ -1286,13 +1282,13 @@ dp_status sim_export_ilu(dp_sim* sim, int32_t* perm, int32_t* brow, int32_t* bco
     for (int pos = 0; pos < nb; ++pos) {
         put(pos, pos, ui[pos]);
         if (pos < n) {
-            put(pos, n + t.h_frow_of_cell[pos], Am[pos]);
+            put(pos, n + pos, Am[pos]);
         } else if (pos < 2 * n) {
             int q = pos - n;
             bool red = q < t.nred;
             for (int sl = 0; sl < 6; ++sl)
                 if (t.h_fmask[q] & (1u << sl)) put(pos, t.h_fcol[(size_t)sl * n + q], red ? Af[(size_t)sl * n + q] : l[(size_t)sl * n + q]);
-            put(pos, t.h_fcell[q], l[(size_t)6 * n + q]);
+            put(pos, q, l[(size_t)6 * n + q]);
             int p = t.h_fperf[q];
             if (p >= 0) put(pos, 2 * n + t.h_perf_well[p], ubw[p]);
         } else {

@@ -104,6 +104,29 @@ def test_default_ordering_matrix_nodes_eliminated_exactly():
     assert np.allclose(np.linalg.inv(ilu.uinv[i]), schur, rtol=1e-12)
 
 
+def test_bilu0_does_not_depend_on_the_order_of_the_matrix_nodes():
+    """The matrix nodes are mutually uncoupled, so listing them in another order
+    (still before every fracture node) gives the same L and U blocks and the
+    same inverted diagonals, block for block in canonical indices."""
+    geo, J, b = _system(synth.model_small())
+    indptr, indices, data = ph.to_bsr(geo, J)
+    dh, _ = cpr.decouple(2 * geo.n, indptr, indices, data, b)
+    perm = cpr.default_ordering(geo)
+    other = perm.copy()
+    other[:geo.n] = np.random.default_rng(5).permutation(perm[:geo.n])
+    assert not np.array_equal(other, perm)
+    ilus = [cpr.BlockILU0(indptr, indices, dh, p) for p in (perm, other)]
+    blocks = []
+    for ilu in ilus:
+        d = {(int(ilu.perm[i]), int(ilu.perm[c])): v for i, c, v in ilu.factors()}
+        for i in range(ilu.nb):
+            d[("inv", int(ilu.perm[i]))] = ilu.uinv[i]
+        blocks.append(d)
+    assert blocks[0].keys() == blocks[1].keys()
+    for key, v in blocks[0].items():
+        assert np.array_equal(v, blocks[1][key]), key
+
+
 def _poisson2d(nx, ny, shift=0.0, rng=None):
     n = nx * ny
     rows, cols, vals = [], [], []
