@@ -216,7 +216,7 @@ __global__ void __launch_bounds__(256) spmv_kernel(SpArgs<T> a, int bm, int bf) 
     int b = blockIdx.x;
     int n = a.n;
     if (b < bm) {
-        int c = b * blockDim.x + threadIdx.x;
+        int c = xcd_block(b, bm) * blockDim.x + threadIdx.x;
         if (c >= n) return;
         T y0 = 0, y1 = 0;
         V2<T> xs = xval<T, MODE>(a, c);
@@ -224,7 +224,7 @@ __global__ void __launch_bounds__(256) spmv_kernel(SpArgs<T> a, int bm, int bf) 
         acc_blk<T, MODE>(a.A.m0, a.A.m1, c, xval<T, MODE>(a, n + c), y0, y1);
         sp_store<T, MODE>(a, c, y0, y1, xs);
     } else if (b < bm + bf) {
-        int q = (b - bm) * blockDim.x + threadIdx.x;
+        int q = xcd_block(b - bm, bf) * blockDim.x + threadIdx.x;
         if (q >= n) return;
         int row = n + q;
         T y0 = 0, y1 = 0;
@@ -274,7 +274,7 @@ __global__ void __launch_bounds__(256) presid_red_kernel(SpArgs<T> a, int bf, T*
     int b = blockIdx.x;
     int n = a.n;
     if (b < bf) {
-        int q = b * blockDim.x + threadIdx.x;
+        int q = xcd_block(b, bf) * blockDim.x + threadIdx.x;
         if (q >= n) return;
         int row = n + q;
         int c = q;  // the matrix node of fracture row q
