@@ -30,7 +30,9 @@ Readings of what the paper leaves open:
   smoothing; coarsest level solved exactly.
 * GMRES: right-preconditioned, restart 30, classical Gram-Schmidt with one
   re-orthogonalisation pass, Givens rotations; the tolerance is on the
-  decoupled residual.
+  decoupled residual.  The re-orthogonalisation correction and the
+  normalisation of each new basis vector are deferred to the next iteration
+  (see gmres), which leaves the Hessenberg columns those of CGS2.
 """
 import numpy as np
 import scipy.sparse as sp
@@ -459,9 +461,24 @@ class CPRFPF:
 
 def gmres(matvec, precond, b, rtol, restart=30, maxit=300, x0=None, trace=None):
     """Right-preconditioned restarted GMRES with CGS2 Arnoldi and Givens
-    rotations.  Returns (x, iterations, relative true residual).  If ``trace``
-    is a dict, the first cycle's V, Z and (unrotated) Hessenberg matrix are
-    stored in it."""
+    rotations.  Returns (x, iterations, relative true residual).
+
+    Iteration j projects w = A z_j on the orthonormal basis v_0..v_j
+    (h = V^T w, w' = w - V h) and measures what is left (a = V^T w',
+    n2 = |w'|^2).  Column j of the Hessenberg matrix is h + a with
+    subdiagonal alpha = sqrt(n2 - |a|^2): the coefficients and the norm of
+    classical Gram-Schmidt with one re-orthogonalisation pass, the norm by the
+    Pythagorean relation (V orthonormal).  The corrected vector
+    v_{j+1} = (w' - V a) / alpha is formed at the start of the next iteration,
+    together with that iteration's projections, and the preconditioner of
+    iteration j+1 is applied to w' scaled to unit length:
+    z_{j+1} = M^-1 (w' / sqrt(n2)).  The relation A Z = V H holds for the
+    stored Z whichever vector z_{j+1} was made from, so the least-squares step
+    is that of GMRES; span(Z) differs from the Krylov space of the v's only by
+    the rounding-size a.
+
+    If ``trace`` is a dict, the first cycle's V (its last vector formed), Z
+    and (unrotated) Hessenberg matrix are stored in it."""
     n = b.shape[0]
     x = np.zeros(n) if x0 is None else x0.copy()
     bnorm = np.linalg.norm(b)
@@ -480,18 +497,23 @@ def gmres(matvec, precond, b, rtol, restart=30, maxit=300, x0=None, trace=None):
         g = np.zeros(restart + 1)
         g[0] = beta
         V[0] = r / beta
+        pending = V[0]          # the vector the next preconditioner step takes
+        scale = 1.0             # ... scaled by this
+        a_prev, alpha_prev = None, 1.0
         k = 0
         for j in range(restart):
-            Z[j] = precond(V[j])
+            Z[j] = precond(pending * scale)
             w = matvec(Z[j])
+            if j > 0:
+                V[j] = (pending - V[:j].T @ a_prev) / alpha_prev
             h = V[:j + 1] @ w
             w = w - V[:j + 1].T @ h
-            h2 = V[:j + 1] @ w
-            w = w - V[:j + 1].T @ h2
-            h = h + h2
-            hn = np.linalg.norm(w)
+            a = V[:j + 1] @ w
+            n2 = w @ w
+            d = n2 - a @ a
+            hn = np.sqrt(d) if d > 0.0 else 0.0
             col = np.zeros(restart + 1)
-            col[:j + 1] = h
+            col[:j + 1] = h + a
             col[j + 1] = hn
             Hraw[:, j] = col
             for i in range(j):
@@ -508,11 +530,12 @@ def gmres(matvec, precond, b, rtol, restart=30, maxit=300, x0=None, trace=None):
             H[:, j] = col
             its += 1
             k = j + 1
+            pending, a_prev, alpha_prev = w, a, hn
+            scale = 1.0 / np.sqrt(n2) if n2 > 0.0 else 0.0
             if hn == 0.0 or abs(g[j + 1]) <= rtol * bnorm or its >= maxit:
                 break
-            V[j + 1] = w / hn
         if trace is not None and "V" not in trace:
-            V[k] = w / hn if hn != 0.0 else 0.0
+            V[k] = (pending - V[:k].T @ a_prev) / alpha_prev if alpha_prev != 0.0 else 0.0
             trace.update(V=V[:k + 1].copy(), Z=Z[:k].copy(), H=Hraw[:k + 1, :k].copy())
         y = np.linalg.solve(np.triu(H[:k, :k]), g[:k])
         x = x + Z[:k].T @ y

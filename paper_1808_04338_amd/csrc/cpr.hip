@@ -94,12 +94,15 @@ static void capture_precond(dp_sim* s) {
 
 constexpr int64_t PRECOND_GRAPH_DOF = 1000000;  // auto mode: graphs below this many unknowns
 
-void cpr_apply(dp_sim* s, const double* r, double* z) {
+void cpr_apply(dp_sim* s, const double* r, double* z, double scale) {
     int64_t len = 2 * (int64_t)s->topo.nb;
     // graphs pay where launches dominate: small systems (auto), or when forced
     const int mode = s->desc.precond_eager;
     const bool graph = !s->timing && (mode == 2 || (mode == 0 && len < PRECOND_GRAPH_DOF));
-    if (s->fp32) to_f32(s, r, (float*)s->pr, len);
+    // the core reads the handle's buffer pr, except unscaled eager FP64 (r itself)
+    const bool own = s->fp32 || graph || scale != 1.0;
+    if (s->fp32) to_f32(s, r, (float*)s->pr, len, scale);
+    else if (scale != 1.0) vec_scale_to(s, r, scale, (double*)s->pr, len);
     else if (graph) copy_f64(s, r, (double*)s->pr, len);
     if (graph) {
         if (!s->pc_graph_ok) capture_precond(s);
@@ -107,7 +110,7 @@ void cpr_apply(dp_sim* s, const double* r, double* z) {
     } else if (s->fp32) {
         apply_core<float>(s, (const f2*)s->pr);
     } else {
-        apply_core<double>(s, (const d2*)r);
+        apply_core<double>(s, own ? (const d2*)s->pr : (const d2*)r);
     }
     if (s->fp32) add_to_f64(s, (const float*)s->pz2, (const float*)s->pz, z, len);
     else vec_add3<double>(s, (const double*)s->pz2, (const double*)s->pz, z, len);

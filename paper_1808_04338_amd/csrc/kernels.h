@@ -43,16 +43,19 @@ void vec_copy(dp_sim* s, const double* x, double* y, int64_t len);
 void vec_zero(dp_sim* s, double* x, int64_t len);
 void vec_scale_to(dp_sim* s, const double* x, double alpha, double* y, int64_t len);
 void vec_axpy(dp_sim* s, double alpha, const double* x, double* y, int64_t len);
-void to_f32(dp_sim* s, const double* x, float* y, int64_t len);
+void to_f32(dp_sim* s, const double* x, float* y, int64_t len, double a = 1.0);  // y = (float)(a x)
 void to_f64(dp_sim* s, const float* x, double* y, int64_t len);
 void add_to_f64(dp_sim* s, const float* a, const float* b, double* y, int64_t len);
 template <class T> void vec_add3(dp_sim* s, const T* a, const T* b, T* y, int64_t len);
 // reductions: results land in s->red_out (device) and are copied to s->red_host
+// out_i = V_i . w (i < k)
 void dot_multi(dp_sim* s, const double* V, int64_t ld, int k, const double* w, int64_t len, double* out);
-void cgs_update_dot(dp_sim* s, const double* V, int64_t ld, int k, const double* h, double* w,
-                    int64_t len, double* out);
-void cgs_update_norm(dp_sim* s, const double* V, int64_t ld, int k, const double* h, double* w,
-                     int64_t len, double* out);
+// u = w - sum_i h_i V_i; out_i = V_i . u (i < k), out_k = u . u
+void gs_update_dot_norm(dp_sim* s, const double* V, int64_t ld, int k, const double* h, const double* w,
+                        double* u, int64_t len, double* out);
+// V_k = (V_k - sum_i a_i V_i) * sc in place; out_i = V_i . w (i <= k)
+void gs_finish_dot(dp_sim* s, double* V, int64_t ld, int k, const double* a, double sc, const double* w,
+                   int64_t len, double* out);
 void norm2(dp_sim* s, const double* x, int64_t len, double* out);
 void combine(dp_sim* s, const double* Z, int64_t ld, int k, const double* y, double* x, int64_t len);
 
@@ -64,6 +67,6 @@ void amg_release(dp_sim* s);
 
 // cpr.hip
 void cpr_setup(dp_sim* s);
-void cpr_apply(dp_sim* s, const double* r, double* z);  // FP64 in/out, [2nb]
+void cpr_apply(dp_sim* s, const double* r, double* z, double scale = 1.0);  // z = M^-1 (scale r), FP64 [2nb]
 
 }  // namespace dp

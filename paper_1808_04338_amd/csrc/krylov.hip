@@ -27,28 +27,37 @@ __device__ inline double block_sum(double v, double* sh) {
 }
 
 // OP 0: out_k = V_k . w                           (k < nv)
-// OP 1: w -= sum_k h_k V_k; out_k = V_k . w        (one read of every V_k)
-// OP 2: w -= sum_k h_k V_k; out_0 = w . w
+// OP 1: u = w - sum_k h_k V_k; out_k = V_k . u (k < nv), out_nv = u . u;
+//       u is written to wout (one read of every V_k)
 // OP 3: out_0 = w . w
+// OP 4: V_nv = (V_nv - sum_k h_k V_k) * sc, written in place; out_k = V_k . w
+//       for k <= nv, the last with the new V_nv (one read of every V_k)
 // NV bounds nv at compile time so that the per-thread accumulators of a short
 // basis stay few (occupancy); every thread handles (x, y) pairs (16-byte loads).
 // len is even and V, w are 16-byte aligned with an even leading dimension.
+template <int OP>
+__host__ __device__ constexpr int red_results(int nv) {
+    return OP == 3 ? 1 : (OP == 0 ? nv : nv + 1);
+}
+
 template <int OP, int NV>
-__global__ void __launch_bounds__(RBLK) red_kernel(const double* __restrict__ V, int64_t ld, int nv,
-                                                   const double* __restrict__ h, double* w, int64_t len,
-                                                   double* part) {
-    __shared__ double sh[NV][RBLK / WAVE];
+__global__ void __launch_bounds__(RBLK) red_kernel(double* V, int64_t ld, int nv,
+                                                   const double* __restrict__ h, double sc, double* w,
+                                                   double* wout, int64_t len, double* part) {
+    constexpr int NR = NV + 1;
+    __shared__ double sh[NR][RBLK / WAVE];
     double acc[NV];
+    double extra = 0.0;  // result nv of OP 1 and OP 4, result 0 of OP 3
     double hh[NV];
 #pragma unroll
-    for (int k = 0; k < NV; ++k) {
-        acc[k] = 0.0;
-        hh[k] = (OP == 1 || OP == 2) && k < nv ? h[k] : 0.0;
-    }
+    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) hh[k] = (OP == 1 || OP == 4) && k < nv ? h[k] : 0.0;
     const int64_t half = len >> 1;
     const int64_t ld2 = ld >> 1;
-    const double2* V2 = reinterpret_cast<const double2*>(V);
-    double2* w2 = reinterpret_cast<double2*>(w);
+    double2* V2 = reinterpret_cast<double2*>(V);
+    const double2* w2 = reinterpret_cast<const double2*>(w);
+    double2* o2 = reinterpret_cast<double2*>(wout);
     const int64_t stride = (int64_t)gridDim.x * RBLK;
     for (int64_t i = (int64_t)blockIdx.x * RBLK + threadIdx.x; i < half; i += stride) {
         double2 wi = w2[i];
@@ -69,30 +78,41 @@ __global__ void __launch_bounds__(RBLK) red_kernel(const double* __restrict__ V,
                     wi.x -= hh[k] * v[k].x;
                     wi.y -= hh[k] * v[k].y;
                 }
-            w2[i] = wi;
+            o2[i] = wi;
 #pragma unroll
             for (int k = 0; k < NV; ++k)
                 if (k < nv) acc[k] += v[k].x * wi.x + v[k].y * wi.y;
-        } else if (OP == 2) {
+            extra += wi.x * wi.x + wi.y * wi.y;
+        } else if (OP == 4) {
+            double2 v[NV];
+#pragma unroll
+            for (int k = 0; k < NV; ++k) v[k] = k < nv ? V2[k * ld2 + i] : make_double2(0.0, 0.0);
+            double2 p = V2[nv * ld2 + i];
 #pragma unroll
             for (int k = 0; k < NV; ++k)
                 if (k < nv) {
-                    double2 v = V2[k * ld2 + i];
-                    wi.x -= hh[k] * v.x;
-                    wi.y -= hh[k] * v.y;
+                    p.x -= hh[k] * v[k].x;
+                    p.y -= hh[k] * v[k].y;
                 }
-            w2[i] = wi;
-            acc[0] += wi.x * wi.x + wi.y * wi.y;
+            p.x *= sc;
+            p.y *= sc;
+            V2[nv * ld2 + i] = p;
+#pragma unroll
+            for (int k = 0; k < NV; ++k)
+                if (k < nv) acc[k] += v[k].x * wi.x + v[k].y * wi.y;
+            extra += p.x * wi.x + p.y * wi.y;
         } else {
-            acc[0] += wi.x * wi.x + wi.y * wi.y;
+            extra += wi.x * wi.x + wi.y * wi.y;
         }
     }
-    const int nres = (OP == 0 || OP == 1) ? nv : 1;
+    // result k: dot k for k < nv (OP 3: none), then the extra one
+    const int nd = OP == 3 ? 0 : nv;
+    const int nres = red_results<OP>(nv);
     const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
 #pragma unroll
-    for (int k = 0; k < NV; ++k) {
+    for (int k = 0; k < NR; ++k) {
         if (k < nres) {
-            double v = wave_sum(acc[k]);
+            double v = wave_sum(k < nd ? acc[k < NV ? k : NV - 1] : extra);
             if (lane == 0) sh[k][wv] = v;
         }
     }
@@ -107,21 +127,21 @@ __global__ void __launch_bounds__(RBLK) red_kernel(const double* __restrict__ V,
 
 // out[k] = sum over the nblk block partials of result k, for k < nres: thread t
 // adds blocks t, t + RBLK, ... (independent loads), then a block reduction.
-template <int NV>
+template <int NR>
 __global__ void __launch_bounds__(RBLK) red_final(const double* __restrict__ part, int nblk, int nres,
                                                   double* out) {
-    __shared__ double sh[NV][RBLK / WAVE];
+    __shared__ double sh[NR][RBLK / WAVE];
     const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
-    double acc[NV];
+    double acc[NR];
 #pragma unroll
-    for (int k = 0; k < NV; ++k) acc[k] = 0.0;
+    for (int k = 0; k < NR; ++k) acc[k] = 0.0;
     for (int b = threadIdx.x; b < nblk; b += RBLK) {
 #pragma unroll
-        for (int k = 0; k < NV; ++k)
+        for (int k = 0; k < NR; ++k)
             if (k < nres) acc[k] += part[(int64_t)b * KMAX + k];
     }
 #pragma unroll
-    for (int k = 0; k < NV; ++k) {
+    for (int k = 0; k < NR; ++k) {
         if (k < nres) {
             double v = wave_sum(acc[k]);
             if (lane == 0) sh[k][wv] = v;
@@ -144,48 +164,48 @@ static int red_grid(int64_t len) {
 }
 
 template <int OP, int NV>
-static void red_go(dp_sim* s, int g, const double* V, int64_t ld, int nv, const double* h, double* w,
-                   int64_t len, double* out) {
-    red_kernel<OP, NV><<<g, RBLK, 0, s->stream>>>(V, ld, nv, h, w, len, s->red_part);
-    red_final<NV><<<1, RBLK, 0, s->stream>>>(s->red_part, g, (OP == 0 || OP == 1) ? nv : 1, out);
+static void red_go(dp_sim* s, int g, double* V, int64_t ld, int nv, const double* h, double sc, double* w,
+                   double* wout, int64_t len, double* out) {
+    red_kernel<OP, NV><<<g, RBLK, 0, s->stream>>>(V, ld, nv, h, sc, w, wout, len, s->red_part);
+    red_final<NV + 1><<<1, RBLK, 0, s->stream>>>(s->red_part, g, red_results<OP>(nv), out);
 }
 
 template <int OP>
-static void red_launch(dp_sim* s, const double* V, int64_t ld, int nv, const double* h, double* w,
-                       int64_t len, double* out) {
-    if (nv > KMAX) fail(DP_E_INVALID, "too many Krylov vectors");
+static void red_launch(dp_sim* s, double* V, int64_t ld, int nv, const double* h, double sc, double* w,
+                       double* wout, int64_t len, double* out) {
+    if (nv < 0 || red_results<OP>(nv) > KMAX || (OP == 4 && nv + 1 > KMAX)) fail(DP_E_INVALID, "too many Krylov vectors");
     if ((len & 1) || (ld & 1)) fail(DP_E_INVALID, "Krylov vectors must have even length");
     int g = red_grid(len);
     if (g > s->red_blocks) fail(DP_E_INVALID, "reduction buffer too small");
     if constexpr (OP == 3) {
-        red_go<OP, 1>(s, g, V, ld, nv, h, w, len, out);
+        red_go<OP, 1>(s, g, V, ld, nv, h, sc, w, wout, len, out);
     } else if (nv <= 2) {
-        red_go<OP, 2>(s, g, V, ld, nv, h, w, len, out);
+        red_go<OP, 2>(s, g, V, ld, nv, h, sc, w, wout, len, out);
     } else if (nv <= 4) {
-        red_go<OP, 4>(s, g, V, ld, nv, h, w, len, out);
+        red_go<OP, 4>(s, g, V, ld, nv, h, sc, w, wout, len, out);
     } else if (nv <= 8) {
-        red_go<OP, 8>(s, g, V, ld, nv, h, w, len, out);
+        red_go<OP, 8>(s, g, V, ld, nv, h, sc, w, wout, len, out);
     } else if (nv <= 16) {
-        red_go<OP, 16>(s, g, V, ld, nv, h, w, len, out);
+        red_go<OP, 16>(s, g, V, ld, nv, h, sc, w, wout, len, out);
     } else {
-        red_go<OP, KMAX>(s, g, V, ld, nv, h, w, len, out);
+        red_go<OP, KMAX>(s, g, V, ld, nv, h, sc, w, wout, len, out);
     }
     DP_LAUNCH_CHECK();
 }
 
 void dot_multi(dp_sim* s, const double* V, int64_t ld, int k, const double* w, int64_t len, double* out) {
-    red_launch<0>(s, V, ld, k, nullptr, const_cast<double*>(w), len, out);
+    red_launch<0>(s, const_cast<double*>(V), ld, k, nullptr, 1.0, const_cast<double*>(w), nullptr, len, out);
 }
-void cgs_update_dot(dp_sim* s, const double* V, int64_t ld, int k, const double* h, double* w,
-                    int64_t len, double* out) {
-    red_launch<1>(s, V, ld, k, h, w, len, out);
+void gs_update_dot_norm(dp_sim* s, const double* V, int64_t ld, int k, const double* h, const double* w,
+                        double* u, int64_t len, double* out) {
+    red_launch<1>(s, const_cast<double*>(V), ld, k, h, 1.0, const_cast<double*>(w), u, len, out);
 }
-void cgs_update_norm(dp_sim* s, const double* V, int64_t ld, int k, const double* h, double* w,
-                     int64_t len, double* out) {
-    red_launch<2>(s, V, ld, k, h, w, len, out);
+void gs_finish_dot(dp_sim* s, double* V, int64_t ld, int k, const double* a, double sc, const double* w,
+                   int64_t len, double* out) {
+    red_launch<4>(s, V, ld, k, a, sc, const_cast<double*>(w), nullptr, len, out);
 }
 void norm2(dp_sim* s, const double* x, int64_t len, double* out) {
-    red_launch<3>(s, nullptr, 0, 1, nullptr, const_cast<double*>(x), len, out);
+    red_launch<3>(s, nullptr, 0, 1, nullptr, 1.0, const_cast<double*>(x), nullptr, len, out);
 }
 
 // x += sum_k y_k Z_k
@@ -219,9 +239,9 @@ __global__ void zero_kernel(double* x, int64_t len) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < len) x[i] = 0.0;
 }
-__global__ void f32_kernel(const double* __restrict__ x, float* y, int64_t len) {
+__global__ void f32_kernel(const double* __restrict__ x, double a, float* y, int64_t len) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < len) y[i] = (float)x[i];
+    if (i < len) y[i] = (float)(a * x[i]);
 }
 __global__ void f64_kernel(const float* __restrict__ x, double* y, int64_t len) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -277,8 +297,8 @@ void vec_axpy(dp_sim* s, double alpha, const double* x, double* y, int64_t len) 
     axpy_kernel<<<ceil_div(len, 256), 256, 0, s->stream>>>(alpha, x, y, len);
     DP_LAUNCH_CHECK();
 }
-void to_f32(dp_sim* s, const double* x, float* y, int64_t len) {
-    f32_kernel<<<ceil_div(len, 256), 256, 0, s->stream>>>(x, y, len);
+void to_f32(dp_sim* s, const double* x, float* y, int64_t len, double a) {
+    f32_kernel<<<ceil_div(len, 256), 256, 0, s->stream>>>(x, a, y, len);
     DP_LAUNCH_CHECK();
 }
 void to_f64(dp_sim* s, const float* x, double* y, int64_t len) {

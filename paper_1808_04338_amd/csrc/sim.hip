@@ -395,7 +395,12 @@ struct PhaseScope {
 // ---------------------------------------------------------------------------
 // GMRES(m), right-preconditioned with CPR-FPF, classical Gram-Schmidt with one
 // re-orthogonalisation pass, Givens rotations on the host.  Solves A y = b with
-// b = s->rhs into s->dx from y = 0.
+// b = s->rhs into s->dx from y = 0.  Two passes over the basis per iteration:
+// the re-orthogonalisation correction and the normalisation of w' are applied
+// in the next iteration's first pass (which reads the basis anyway), the norm
+// of the corrected vector comes from the Pythagorean relation, and the
+// preconditioner takes w' / |w'|; the Hessenberg columns are CGS2's and
+// A Z = V H holds for the stored Z.  One host synchronisation per iteration.
 // ---------------------------------------------------------------------------
 static int gmres(dp_sim* s, double rtol, int maxit, int* iters, double* rel_res) {
     int nb = s->topo.nb;
@@ -404,7 +409,7 @@ static int gmres(dp_sim* s, double rtol, int maxit, int* iters, double* rel_res)
     double* b = (double*)s->rhs;
     double* x = (double*)s->dx;
     double* r = s->w;
-    double* hb = s->red_out;  // [0,32) h1, [32,64) h2, [64] |w|^2, [96] norms
+    double* hb = s->red_out;  // [0,32) h, [32,64) a and |w'|^2, [96] norms
     vec_zero(s, x, len);
     norm2(s, b, len, hb + 96);
     double hn2 = 0;
@@ -419,18 +424,22 @@ static int gmres(dp_sim* s, double rtol, int maxit, int* iters, double* rel_res)
     double beta = bnorm;
     const double* rvec = b;
     int its = 0;
-    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), hbuf(97);
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), hbuf(64);
     while (beta > rtol * bnorm && its < maxit) {
         vec_scale_to(s, rvec, 1.0 / beta, s->V, len);
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = beta;
         int k = 0;
+        double scale = 1.0;      // the preconditioner's input is the slot's vector times this
+        double inv_alpha = 1.0;  // 1 / |w'' | of the vector pending in slot j
         for (int j = 0; j < m; ++j) {
+            // slot j holds v_j (j = 0) or the previous iteration's w', still to be
+            // corrected and normalised; the preconditioner takes w' / |w'|
             double* vj = s->V + (int64_t)j * len;
             double* zj = s->Z + (int64_t)j * len;
             {
                 PhaseScope ps(s, 4);
-                cpr_apply(s, vj, zj);
+                cpr_apply(s, vj, zj, scale);
             }
             {
                 PhaseScope ps(s, 3);
@@ -438,20 +447,30 @@ static int gmres(dp_sim* s, double rtol, int maxit, int* iters, double* rel_res)
                 bspmv<double>(s, (const d2*)zj, (d2*)r);
                 ks.bytes(kernel_bytes(s, 0));
             }
-            dot_multi(s, s->V, len, j + 1, r, len, hb);
-            cgs_update_dot(s, s->V, len, j + 1, hb, r, len, hb + 32);
-            cgs_update_norm(s, s->V, len, j + 1, hb + 32, r, len, hb + 64);
-            DP_HIP(hipMemcpyAsync(hbuf.data(), hb, sizeof(double) * 65, hipMemcpyDeviceToHost, s->stream));
+            // h = V^T w over v_0..v_j; for j > 0 the same pass first forms
+            // v_j = (w' - V a) / alpha in place from the previous a (at hb + 32)
+            if (j == 0) dot_multi(s, s->V, len, 1, r, len, hb);
+            else gs_finish_dot(s, s->V, len, j, hb + 32, inv_alpha, r, len, hb);
+            // w' = w - V h into slot j + 1, a = V^T w' and |w'|^2 (at hb + 32)
+            gs_update_dot_norm(s, s->V, len, j + 1, hb, r, s->V + (int64_t)(j + 1) * len, len, hb + 32);
+            DP_HIP(hipMemcpyAsync(hbuf.data(), hb, sizeof(double) * 64, hipMemcpyDeviceToHost, s->stream));
             DP_HIP(hipStreamSynchronize(s->stream));
-            double hn = std::sqrt(hbuf[64]);
+            // column j: CGS2's coefficients h + a, and |w' - V a| by the
+            // Pythagorean relation (V orthonormal)
+            double n2 = hbuf[32 + j + 1], aa = 0.0;
             std::vector<double> col(m + 1, 0.0);
-            for (int i = 0; i <= j; ++i) col[i] = hbuf[i] + hbuf[32 + i];
-            col[j + 1] = hn;
-            if (!std::isfinite(hn)) {
+            for (int i = 0; i <= j; ++i) {
+                col[i] = hbuf[i] + hbuf[32 + i];
+                aa += hbuf[32 + i] * hbuf[32 + i];
+            }
+            if (!std::isfinite(n2) || !std::isfinite(aa)) {
                 *iters = its;
                 *rel_res = NAN;
                 return DP_E_NUMERIC;
             }
+            double d = n2 - aa;
+            double hn = d > 0.0 ? std::sqrt(d) : 0.0;
+            col[j + 1] = hn;
             for (int i = 0; i < j; ++i) {
                 double tt = cs[i] * col[i] + sn[i] * col[i + 1];
                 col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
@@ -468,7 +487,8 @@ static int gmres(dp_sim* s, double rtol, int maxit, int* iters, double* rel_res)
             ++its;
             k = j + 1;
             if (hn == 0.0 || std::fabs(g[j + 1]) <= rtol * bnorm || its >= maxit) break;
-            vec_scale_to(s, r, 1.0 / hn, s->V + (int64_t)(j + 1) * len, len);
+            inv_alpha = 1.0 / hn;
+            scale = 1.0 / std::sqrt(n2);
         }
         for (int i = k - 1; i >= 0; --i) {
             double acc = g[i];

@@ -250,7 +250,34 @@ def test_gmres_arnoldi_relation_and_orthogonality():
     lhs = AZ.T
     rhs = V.T @ H
     assert np.linalg.norm(lhs - rhs) <= 1e-12 * spla.norm(A) * np.sqrt(k)
-    assert np.abs(V @ V.T - np.eye(V.shape[0])).max() <= 1e-12
+    # 1e-14 needs the re-orthogonalisation: a single classical Gram-Schmidt
+    # pass leaves about 3e-13 on this problem
+    assert np.abs(V @ V.T - np.eye(V.shape[0])).max() <= 1e-14
+
+
+def test_gmres_iterate_minimises_the_residual_over_the_krylov_space():
+    """After k < n iterations (no restart) the iterate is x = M^-1 K c with K the
+    Krylov basis [r, (A M^-1) r, ..., (A M^-1)^(k-1) r] and c minimising
+    |b - A M^-1 K c|, found here by a dense least-squares solve on the explicit
+    (column-scaled) basis."""
+    rng = np.random.default_rng(11)
+    n = 60
+    A = (sp.diags(np.linspace(1.0, 4.0, n)) + 0.3 * sp.random(n, n, density=0.1, random_state=5)).tocsr()
+    b = rng.standard_normal(n)
+    d = 1.0 / A.diagonal()
+    for k in (1, 3, 6):
+        x, its, rel = cpr.gmres(lambda v: A @ v, lambda v: d * v, b, 1e-15, restart=30, maxit=k)
+        assert its == k
+        K = np.zeros((n, k))
+        v = b.copy()
+        for i in range(k):
+            K[:, i] = v / np.linalg.norm(v)
+            v = A @ (d * K[:, i])
+        MK = d[:, None] * K
+        c, *_ = np.linalg.lstsq(A @ MK, b, rcond=None)
+        xref = MK @ c
+        assert np.linalg.norm(x - xref) <= 1e-9 * np.linalg.norm(xref)
+        assert abs(rel - np.linalg.norm(b - A @ xref) / np.linalg.norm(b)) <= 1e-9
 
 
 def test_gmres_finite_termination_diagonal():
