@@ -256,9 +256,11 @@ dp_status sim_amg_info(dp_sim *sim, int32_t *levels, int32_t *rows, int64_t *nnz
  * rec (host) and stores the full count. */
 dp_status sim_eta_history(dp_sim *sim, double *rec, int32_t cap, int32_t *count);
 
-/* Setup statistics since sim_create: the number of AMG products (interpolation
- * or Galerkin, one per level and setup) that had a row too long for the
- * row-wise LDS path and were formed by the global sort path instead. */
+/* Setup statistics since sim_create: the number of AMG sort-and-sum steps
+ * (interpolation rows, R = P^T, A P and R (A P), per level and setup) that had
+ * rows too long for the row-wise LDS tiles (more than 4096 terms).  Those rows
+ * are sorted by the global radix sort, to the same result; the other rows stay
+ * in the tiles. */
 dp_status sim_amg_stats(dp_sim *sim, int64_t *global_sort_products);
 
 /* Level l: splitting cf[rows[l]] (1 = C, -1 = F; not for the coarsest), the

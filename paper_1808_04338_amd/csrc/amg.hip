@@ -1045,7 +1045,7 @@ void amg_setup(dp_sim* s) {
                                                                       pval, ecnt, wc, wv);
                 seg_off_from_entries<<<ceil_div(n + 1, 256), 256, 0, st>>>(A.rowptr, ecnt, n, A.nnz, m, woff);
                 DP_LAUNCH_CHECK();
-                done = seg_sort_reduce(st, woff, n, nc, wc, wv, m, Sc, Sc, W, "interp W");
+                done = seg_sort_reduce(st, woff, n, nc, wc, wv, m, Sc, Sc, W, "interp W", &s->seg_fallbacks);
                 if (!done) Sc.top = wmark;
             }
             if (!done) {
@@ -1108,7 +1108,7 @@ void amg_setup(dp_sim* s) {
                 DP_LAUNCH_CHECK();
             }
             R.ncols = n;
-            if (!seg_sort_reduce(st, roff, nc, n, tcol, tval, m, Sc, H, R, "R")) {
+            if (!seg_sort_reduce(st, roff, nc, n, tcol, tval, m, Sc, H, R, "R", &s->seg_fallbacks)) {
                 // rows beyond the tiles: scatter again (the tiles rewrite the rows they
                 // finished in place), sort in place and take the arrays as R
                 DP_HIP(hipMemsetAsync(cur, 0, sizeof(int) * (nc > 0 ? nc : 1), st));
@@ -1133,8 +1133,8 @@ void amg_setup(dp_sim* s) {
         bool rap_done = false;
         {
             Csr AP;
-            if (seg_product(st, A, L.P, Sc, Sc, AP, "A P", &s->kt[2]))
-                rap_done = seg_product(st, R, AP, Sc, H, Ac, "coarse A", &s->kt[2]);
+            if (seg_product(st, A, L.P, Sc, Sc, AP, "A P", &s->kt[2], &s->seg_fallbacks))
+                rap_done = seg_product(st, R, AP, Sc, H, Ac, "coarse A", &s->kt[2], &s->seg_fallbacks);
             Sc.top = smark;
         }
         if (!rap_done) {

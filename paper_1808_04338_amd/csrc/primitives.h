@@ -30,20 +30,23 @@ int64_t reduce_to_csr(hipStream_t st, const uint64_t* k, const double* v, int64_
 // [off[r], off[r+1]) (off: nrows + 1 entries, m = off[nrows]) are ordered by
 // column, ties in term order; equal columns are summed in term order and zero
 // sums dropped.  col/val are overwritten.  The CSR arrays come from 'out',
-// temporaries from 'sc' (released unless out is sc).  Returns false, with
-// nothing allocated from 'out', when a row holds more terms than one workgroup
-// sorts in LDS (4096); the caller then takes the global sort path.
+// temporaries from 'sc' (released unless out is sc).  Rows with more terms
+// than one workgroup sorts in LDS (4096) are sorted together by the global
+// radix sort, to the same result; *long_products (if given) counts the calls
+// that had such rows.  Returns false, with nothing allocated from 'out', only
+// when the scratch cannot hold those rows' terms; the caller then takes the
+// global sort path for the whole call.
 bool seg_sort_reduce(hipStream_t st, const int64_t* off, int nrows, int ncols, int* col, double* val,
-                     int64_t m, Arena& sc, Arena& out, Csr& csr, const char* what);
+                     int64_t m, Arena& sc, Arena& out, Csr& csr, const char* what,
+                     int64_t* long_products = nullptr);
 
 // C = X Y row by row (terms of row r: X_re Y_ef for the entries e of X's row r
 // and f of Y's row e, summed per column in that order, zero sums dropped).  C
-// comes from 'out', temporaries from 'sc'.  Returns false, with nothing
-// allocated from 'out', when a row of C has more terms than one workgroup
-// sorts in LDS; the caller then takes the global sort path.
+// comes from 'out', temporaries from 'sc'.  Rows longer than the LDS tiles
+// and the return value as for seg_sort_reduce.
 // kt (may be null): live timer of the product's tile kernels.
 bool seg_product(hipStream_t st, const Csr& X, const Csr& Y, Arena& sc, Arena& out, Csr& C, const char* what,
-                 KernelTimer* kt = nullptr);
+                 KernelTimer* kt = nullptr, int64_t* long_products = nullptr);
 
 inline int bits_for(int64_t n) {
     int b = 1;

@@ -11,10 +11,14 @@
 //   * a row that does not fit its group is handled alone by the wavefront when
 //     it has at most SW_MAX terms, else listed for 256-thread workgroups that
 //     take up to SM_MAX terms (25 KB of LDS), then up to SB_MAX (101 KB);
-//   * a longer row makes the call return false (the caller then takes the
-//     global radix-sort path).
+//   * a longer row is listed once more, and the listed rows' terms are sorted
+//     together by the stable global radix sort on (list index, column): the
+//     same order, sums and compaction as a tile, written back in place (the
+//     call returns false, and the caller takes the global path for the whole
+//     product, only when the scratch region cannot hold those terms).
 // Sorting is a bitonic network on 64-bit keys; sums, compaction ranks (ballot
 // prefix counts) and row lengths are deterministic.
+#include <initializer_list>
 #include <type_traits>
 
 #include "primitives.h"
@@ -255,6 +259,7 @@ __global__ void __launch_bounds__(256) seg_block(Src S, const int* __restrict__ 
         if (fits<MAXE>(S, r, r + 1)) {
             tile_run<256, MAXE>(T, S, r, r + 1, cnt);
         } else if (threadIdx.x == 0) {
+            cnt[r] = 0;  // set by the tier (or the global sort) that takes the row
             if (next) next[atomicAdd(nnext, 1)] = r;
             else *overflow = 1;
         }
@@ -303,18 +308,176 @@ __global__ void prod_count(Csr X, Csr Y, int64_t* cnt) {
     if (l == 0) cnt[r] = c;
 }
 
+// ---------------------------------------------------------------------------
+// Rows beyond the largest tile (list of n3 rows).  Their terms are written in
+// term order keyed (list index << cbits | column), sorted by the stable radix
+// sort, summed per run in sorted (= term) order and compacted at the row's
+// term offset exactly as a tile would.
+// ---------------------------------------------------------------------------
+template <class Src>
+__global__ void long_len(Src S, const int* __restrict__ list, int n3, int64_t* len) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n3) len[i] = S.off[list[i] + 1] - S.off[list[i]];
+}
+
+// one workgroup per listed row: X entries in order, each one's Y row spread
+// over the threads
+__global__ void __launch_bounds__(256) long_expand(ProdSrc S, const int* __restrict__ list,
+                                                   const int64_t* __restrict__ loff, int cbits, uint64_t* key,
+                                                   double* val) {
+    const int i = blockIdx.x;
+    const int r = list[i];
+    int64_t o = loff[i];
+    for (int e = S.X.rowptr[r]; e < S.X.rowptr[r + 1]; ++e) {
+        const int k = S.X.col[e];
+        const int a = S.Y.rowptr[k], b = S.Y.rowptr[k + 1];
+        const double xv = S.X.val[e];
+        for (int f = a + (int)threadIdx.x; f < b; f += blockDim.x) {
+            key[o + (f - a)] = ((uint64_t)i << cbits) | (uint64_t)(uint32_t)S.Y.col[f];
+            val[o + (f - a)] = xv * S.Y.val[f];
+        }
+        o += b - a;
+    }
+}
+__global__ void __launch_bounds__(256) long_expand(BufSrc S, const int* __restrict__ list,
+                                                   const int64_t* __restrict__ loff, int cbits, uint64_t* key,
+                                                   double* val) {
+    const int i = blockIdx.x;
+    const int r = list[i];
+    const int64_t b0 = S.off[r], n = S.off[r + 1] - b0, o = loff[i];
+    for (int64_t t = threadIdx.x; t < n; t += blockDim.x) {
+        key[o + t] = ((uint64_t)i << cbits) | (uint64_t)(uint32_t)S.col[b0 + t];
+        val[o + t] = S.val[b0 + t];
+    }
+}
+
+// run heads: the sum of the run in order, and whether it is kept (non-zero)
+__global__ void long_sum(const uint64_t* __restrict__ key, const double* __restrict__ val, int64_t T,
+                         int64_t* keep, double* sum) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T) return;
+    const uint64_t k = key[t];
+    const bool head = t == 0 || key[t - 1] != k;
+    double s = 0.0;
+    if (head)
+        for (int64_t u = t; u < T && key[u] == k; ++u) s += val[u];
+    keep[t] = (head && s != 0.0) ? 1 : 0;
+    sum[t] = s;
+}
+
+// kept heads to the row's term offset (pos: exclusive ranks of keep; loff has
+// n3 + 1 entries); row lengths of the listed rows into cnt
+__global__ void long_counts(const int* __restrict__ list, int n3, const int64_t* __restrict__ loff,
+                            const int64_t* __restrict__ pos, int64_t T, int64_t kept, int64_t* cnt) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n3) return;
+    int64_t a = loff[i], b = loff[i + 1];
+    int64_t pa = a < T ? pos[a] : kept, pb = b < T ? pos[b] : kept;
+    cnt[list[i]] = pb - pa;
+}
+template <class Src>
+__global__ void long_write(Src S, const int* __restrict__ list, const int64_t* __restrict__ loff,
+                           const uint64_t* __restrict__ key, const double* __restrict__ sum,
+                           const int64_t* __restrict__ keep, const int64_t* __restrict__ pos, int64_t T,
+                           int cbits) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= T || !keep[t]) return;
+    const uint64_t k = key[t];
+    const int i = (int)(k >> cbits);
+    const int r = list[i];
+    const int64_t o = S.off[r] + (pos[t] - pos[loff[i]]);
+    const int c = (int)(k & ((1ull << cbits) - 1));
+    if constexpr (std::is_same<Src, ProdSrc>::value) {
+        S.ocol[o] = c;
+        S.oval[o] = sum[t];
+    } else {
+        S.col[o] = c;
+        S.val[o] = sum[t];
+    }
+}
+
+// row lengths back from their exclusive scan (total: the sum)
+__global__ void unscan(const int64_t* __restrict__ ex, int n, int64_t total, int64_t* len) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n) len[r] = (r + 1 < n ? ex[r + 1] : total) - ex[r];
+}
+
+static size_t arena_need(std::initializer_list<size_t> bytes) {
+    size_t t = 0;
+    for (size_t b : bytes) t += ((b + 255) & ~size_t(255)) + 256;
+    return t;
+}
+
+// The listed rows (n3 > 0) of a product whose other rows the tiles finished:
+// cnt holds the exclusive scan of the row lengths (total: its sum; the listed
+// rows counted as empty).  On success cnt points at the scan of
+// the corrected lengths and total is their sum.  Returns false, with the
+// scratch released, when the sort's buffers do not fit.
+template <class Src>
+static bool long_rows(hipStream_t st, const Src& S, const int* list, int n3, int nrows, int ncols,
+                      int64_t*& cnt, int64_t& total, Arena& sc) {
+    const size_t mark = sc.top;
+    if (sc.top + arena_need({8 * (size_t)(n3 + 1), 8 * (size_t)scan_tmp_size(n3 + 1)}) > sc.cap) return false;
+    int64_t* loff = sc.get<int64_t>(n3 + 1, "long rows");
+    int64_t* ltmp = sc.get<int64_t>(scan_tmp_size(n3 + 1), "scan tmp");
+    long_len<Src><<<ceil_div(n3, 256), 256, 0, st>>>(S, list, n3, loff);
+    DP_LAUNCH_CHECK();
+    int64_t T = 0;
+    exclusive_scan(st, loff, n3, ltmp, &T);
+    seg_set_last<<<1, 1, 0, st>>>(loff, n3, T);
+    DP_LAUNCH_CHECK();
+    const int cbits = bits_for(ncols);
+    const int nbits = bits_for(n3) + cbits;
+    const size_t need = arena_need({8 * (size_t)(nrows + 1), 8 * (size_t)T, 8 * (size_t)T, 8 * (size_t)T,
+                                    8 * (size_t)T, 8 * (size_t)sort_tmp_size(T), 8 * (size_t)(T + 1),
+                                    8 * (size_t)(T + 1), 8 * (size_t)scan_tmp_size(T + 1),
+                                    8 * (size_t)scan_tmp_size(nrows + 1)});
+    if (nbits > 64 || sc.top + need > sc.cap) {
+        sc.top = mark;
+        return false;
+    }
+    int64_t* len = sc.get<int64_t>(nrows + 1, "segment counts");
+    uint64_t* k0 = sc.get<uint64_t>(T, "long row keys");
+    double* v0 = sc.get<double>(T, "long row values");
+    uint64_t* k1 = sc.get<uint64_t>(T, "long row keys");
+    double* v1 = sc.get<double>(T, "long row values");
+    int64_t* rtmp = sc.get<int64_t>(sort_tmp_size(T), "sort tmp");
+    int64_t* keep = sc.get<int64_t>(T + 1, "long row flags");
+    int64_t* pos = sc.get<int64_t>(T + 1, "long row ranks");
+    int64_t* ktmp = sc.get<int64_t>(scan_tmp_size(T + 1), "scan tmp");
+    int64_t* ntmp = sc.get<int64_t>(scan_tmp_size(nrows + 1), "scan tmp");
+    unscan<<<ceil_div(nrows, 256), 256, 0, st>>>(cnt, nrows, total, len);
+    long_expand<<<n3, 256, 0, st>>>(S, list, loff, cbits, k0, v0);
+    DP_LAUNCH_CHECK();
+    const int which = radix_sort(st, k0, v0, k1, v1, T, nbits, rtmp);
+    const uint64_t* ks = which ? k1 : k0;
+    const double* vs = which ? v1 : v0;
+    double* sums = which ? v0 : v1;  // the idle half of the double buffer
+    long_sum<<<ceil_div(T, 256), 256, 0, st>>>(ks, vs, T, keep, sums);
+    DP_LAUNCH_CHECK();
+    DP_HIP(hipMemcpyAsync(pos, keep, sizeof(int64_t) * T, hipMemcpyDeviceToDevice, st));
+    int64_t kept = 0;
+    exclusive_scan(st, pos, T, ktmp, &kept);
+    long_counts<<<ceil_div(n3, 256), 256, 0, st>>>(list, n3, loff, pos, T, kept, len);
+    long_write<Src><<<ceil_div(T, 256), 256, 0, st>>>(S, list, loff, ks, sums, keep, pos, T, cbits);
+    DP_LAUNCH_CHECK();
+    exclusive_scan(st, len, nrows, ntmp, &total);
+    cnt = len;
+    return true;
+}
+
 // Shared driver: runs the tiles, then scans the row lengths and copies the
 // compacted rows (found at off[r] of rcol/rval) into the CSR from 'out'.
 template <class Src>
 static bool seg_run(hipStream_t st, const Src& S, const int64_t* off, int nrows, int ncols, int64_t m,
                     const int* rcol, const double* rval, Arena& sc, Arena& out, Csr& csr, const char* what,
-                    KernelTimer* kt = nullptr, double xbytes = 0.0) {
+                    KernelTimer* kt = nullptr, double xbytes = 0.0, int64_t* long_products = nullptr) {
     if (ncols >= (1 << 28) || nrows >= (1 << 24)) return false;  // key packing
     int64_t* cnt = sc.get<int64_t>(nrows + 1, "segment counts");
     int64_t* tmp = sc.get<int64_t>(scan_tmp_size(nrows + 1), "scan tmp");
     int* longlist = sc.get<int>(nrows, "long rows");
     int* list2 = sc.get<int>(nrows, "long rows");
-    int* flags = sc.get<int>(4, "segment flags");  // [0] long rows, [1] longer rows, [2] overflow
+    int* flags = sc.get<int>(4, "segment flags");  // [0] long rows, [1] longer rows, [2] beyond the tiles
     DP_HIP(hipMemsetAsync(flags, 0, 4 * sizeof(int), st));
     double avg = nrows > 0 ? (double)m / nrows : 0.0;
     int G = avg > 0 ? (int)(SEG_TARGET / avg) : SEG_GMAX;
@@ -333,13 +496,17 @@ static bool seg_run(hipStream_t st, const Src& S, const int64_t* off, int nrows,
             kidx = ks.idx;
             seg_wave<Src><<<ngroups, WAVE, 0, st>>>(S, nrows, G, cnt, longlist, flags);
             seg_block<SM_MAX, Src><<<1024, 256, shm_m, st>>>(S, longlist, flags, cnt, list2, flags + 1, flags + 2);
-            seg_block<SB_MAX, Src><<<256, 256, shm_b, st>>>(S, list2, flags + 1, cnt, nullptr, nullptr, flags + 2);
+            // rows beyond SB_MAX go back to the first list (consumed by then)
+            seg_block<SB_MAX, Src><<<256, 256, shm_b, st>>>(S, list2, flags + 1, cnt, longlist, flags + 2, flags + 3);
             DP_LAUNCH_CHECK();
         }
         // the flags arrive with the scan's synchronisation
         DP_HIP(hipMemcpyAsync(hf, flags, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
         exclusive_scan(st, cnt, nrows, tmp, &total);
-        if (hf[2]) return false;
+        if (hf[2]) {
+            if (!long_rows(st, S, longlist, hf[2], nrows, ncols, cnt, total, sc)) return false;
+            if (long_products) *long_products += 1;
+        }
         // algorithmic bytes: the sources (xbytes), term offsets and row lengths,
         // the results (column and value)
         if (kt && kidx >= 0) kt->bytes += xbytes + 16.0 * (nrows + 1) + 12.0 * total;
@@ -360,16 +527,16 @@ static bool seg_run(hipStream_t st, const Src& S, const int64_t* off, int nrows,
 }
 
 bool seg_sort_reduce(hipStream_t st, const int64_t* off, int nrows, int ncols, int* col, double* val,
-                     int64_t m, Arena& sc, Arena& out, Csr& csr, const char* what) {
+                     int64_t m, Arena& sc, Arena& out, Csr& csr, const char* what, int64_t* long_products) {
     size_t mark = sc.top;
     BufSrc S{off, col, val};
-    bool ok = seg_run(st, S, off, nrows, ncols, m, col, val, sc, out, csr, what);
+    bool ok = seg_run(st, S, off, nrows, ncols, m, col, val, sc, out, csr, what, nullptr, 0.0, long_products);
     if (!ok || &out != &sc) sc.top = mark;
     return ok;
 }
 
 bool seg_product(hipStream_t st, const Csr& X, const Csr& Y, Arena& sc, Arena& out, Csr& C, const char* what,
-                 KernelTimer* kt) {
+                 KernelTimer* kt, int64_t* long_products) {
     size_t mark = sc.top;
     int nrows = X.n;
     int64_t* off = sc.get<int64_t>(nrows + 1, "product rows");
@@ -388,7 +555,7 @@ bool seg_product(hipStream_t st, const Csr& X, const Csr& Y, Arena& sc, Arena& o
     // X read once (row offsets, columns, values), Y's row offsets once per X
     // entry and one Y entry (column, value) per term
     double xbytes = 4.0 * (nrows + 1) + 12.0 * X.nnz + 8.0 * X.nnz + 12.0 * m;
-    bool ok = seg_run(st, S, off, nrows, Y.ncols, m, ocol, oval, sc, out, C, what, kt, xbytes);
+    bool ok = seg_run(st, S, off, nrows, Y.ncols, m, ocol, oval, sc, out, C, what, kt, xbytes, long_products);
     if (!ok || &out != &sc) sc.top = mark;
     return ok;
 }
