@@ -1177,7 +1177,11 @@ void amg_setup(dp_sim* s) {
 // ---------------------------------------------------------------------------
 // V(1,1) cycle
 // ---------------------------------------------------------------------------
-enum { SV_Y = 0, SV_PRE = 1, SV_PROL = 2, SV_POST = 3 };
+// Y: y = A x.  PRE: y = dinv b (one smoothing step from zero), y2 = b - A y.
+// PROL: y += A x.  POST: y = x + dinv (b - A x).  YD (restriction into a level
+// that is smoothed next): y = A x and y2 = dinv y, so that level starts with
+// x = dinv b already formed.  RES: y = b - A x.
+enum { SV_Y = 0, SV_PRE = 1, SV_PROL = 2, SV_POST = 3, SV_YD = 4, SV_RES = 5 };
 
 template <class T, int MODE>
 __global__ void __launch_bounds__(256) sell_kernel(const int* __restrict__ sptr, const int* __restrict__ col,
@@ -1204,6 +1208,11 @@ __global__ void __launch_bounds__(256) sell_kernel(const int* __restrict__ sptr,
         y2[r] = b[r] - acc;
     } else if (MODE == SV_PROL) {  // y += P x
         y[r] += acc;
+    } else if (MODE == SV_YD) {
+        y[r] = acc;
+        y2[r] = dinv[r] * acc;
+    } else if (MODE == SV_RES) {
+        y[r] = b[r] - acc;
     } else {  // y = x + dinv (b - A x)
         y[r] = x[r] + dinv[r] * (b[r] - acc);
     }
@@ -1262,6 +1271,11 @@ __global__ void __launch_bounds__(256) csrv_kernel(const int* __restrict__ rowpt
         y2[r] = b[r] - acc;
     } else if (MODE == SV_PROL) {
         y[r] += acc;
+    } else if (MODE == SV_YD) {
+        y[r] = acc;
+        y2[r] = dinv[r] * acc;
+    } else if (MODE == SV_RES) {
+        y[r] = b[r] - acc;
     } else {
         y[r] = x[r] + dinv[r] * (b[r] - acc);
     }
@@ -1300,8 +1314,13 @@ T* amg_vcycle(dp_sim* s) {
     int L = (int)s->levels.size();
     for (int l = 0; l < L - 1; ++l) {
         AmgLevel& lv = s->levels[l];
-        op_launch<T, SV_PRE>(s, lv.Aop, (T*)lv.dinv, (T*)lv.b, nullptr, (T*)lv.x, (T*)lv.r);
-        op_launch<T, SV_Y>(s, lv.Rop, nullptr, nullptr, (T*)lv.r, (T*)s->levels[l + 1].b, nullptr);
+        AmgLevel& nx = s->levels[l + 1];
+        // level 0 forms x = dinv b itself; the restriction into a smoothed
+        // level forms it there (one gather per entry in the residual instead of two)
+        if (l == 0) op_launch<T, SV_PRE>(s, lv.Aop, (T*)lv.dinv, (T*)lv.b, nullptr, (T*)lv.x, (T*)lv.r);
+        else op_launch<T, SV_RES>(s, lv.Aop, nullptr, (T*)lv.b, (T*)lv.x, (T*)lv.r, nullptr);
+        if (l + 1 < L - 1) op_launch<T, SV_YD>(s, lv.Rop, (T*)nx.dinv, nullptr, (T*)lv.r, (T*)nx.b, (T*)nx.x);
+        else op_launch<T, SV_Y>(s, lv.Rop, nullptr, nullptr, (T*)lv.r, (T*)nx.b, nullptr);
     }
     AmgLevel& co = s->levels[L - 1];
     if (co.n > 0) {
