@@ -125,34 +125,23 @@ __global__ void __launch_bounds__(RBLK) red_kernel(double* V, int64_t ld, int nv
     }
 }
 
-// out[k] = sum over the nblk block partials of result k, for k < nres: thread t
-// adds blocks t, t + RBLK, ... (independent loads), then a block reduction.
-template <int NR>
-__global__ void __launch_bounds__(RBLK) red_final(const double* __restrict__ part, int nblk, int nres,
-                                                  double* out) {
-    __shared__ double sh[NR][RBLK / WAVE];
+// out[k] = sum over the nblk block partials of result k: one workgroup per
+// result; thread t adds blocks t, t + RBLK, ... in order, then a fixed
+// wavefront butterfly and the wavefronts' sums in order.
+__global__ void __launch_bounds__(RBLK) red_final(const double* __restrict__ part, int nblk, double* out) {
+    __shared__ double sh[RBLK / WAVE];
+    const int k = blockIdx.x;
     const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
-    double acc[NR];
-#pragma unroll
-    for (int k = 0; k < NR; ++k) acc[k] = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += RBLK) {
-#pragma unroll
-        for (int k = 0; k < NR; ++k)
-            if (k < nres) acc[k] += part[(int64_t)b * KMAX + k];
-    }
-#pragma unroll
-    for (int k = 0; k < NR; ++k) {
-        if (k < nres) {
-            double v = wave_sum(acc[k]);
-            if (lane == 0) sh[k][wv] = v;
-        }
-    }
+    double acc = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += RBLK) acc += part[(int64_t)b * KMAX + k];
+    double v = wave_sum(acc);
+    if (lane == 0) sh[wv] = v;
     __syncthreads();
-    if ((int)threadIdx.x < nres) {
-        double v = 0.0;
+    if (threadIdx.x == 0) {
+        double t = 0.0;
 #pragma unroll
-        for (int q = 0; q < RBLK / WAVE; ++q) v += sh[threadIdx.x][q];
-        out[threadIdx.x] = v;
+        for (int q = 0; q < RBLK / WAVE; ++q) t += sh[q];
+        out[k] = t;
     }
 }
 
@@ -167,7 +156,7 @@ template <int OP, int NV>
 static void red_go(dp_sim* s, int g, double* V, int64_t ld, int nv, const double* h, double sc, double* w,
                    double* wout, int64_t len, double* out) {
     red_kernel<OP, NV><<<g, RBLK, 0, s->stream>>>(V, ld, nv, h, sc, w, wout, len, s->red_part);
-    red_final<NV + 1><<<1, RBLK, 0, s->stream>>>(s->red_part, g, red_results<OP>(nv), out);
+    if (red_results<OP>(nv) > 0) red_final<<<red_results<OP>(nv), RBLK, 0, s->stream>>>(s->red_part, g, out);
 }
 
 template <int OP>
