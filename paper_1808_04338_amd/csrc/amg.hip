@@ -25,11 +25,19 @@ constexpr int ST_F = -1;
 // only to its own fracture node, so the Schur complement changes only the
 // fracture diagonal: a_ff - a_fm (1/a_mm) a_mf.
 // ---------------------------------------------------------------------------
+// The same values are also written by slot for the fracture rows (st: [8n],
+// faces 0..5, diagonal, well column; zero where absent), in the preconditioner
+// precision, for the V-cycle's stencil form of level 0.
+template <class T>
 __global__ void extract_ap_kernel(BMat<double> A, const int* __restrict__ rowptr,
                                   const int* __restrict__ src, const int* __restrict__ fperf, int n,
-                                  int nr, double* val) {
+                                  int nr, double* val, T* st) {
     int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= nr) return;
+    if (r < n) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) st[(int64_t)k * n + r] = T(0);  // overwritten below where present
+    }
     for (int e = rowptr[r]; e < rowptr[r + 1]; ++e) {
         int code = src[e];
         double v;
@@ -46,14 +54,19 @@ __global__ void extract_ap_kernel(BMat<double> A, const int* __restrict__ rowptr
             v = code < 0 ? A.d0[n + r].x : A.wf0[code].x;
         }
         val[e] = v;
+        if (r < n) st[(int64_t)(code < 6 ? code : code - 1) * n + r] = (T)v;
     }
 }
 
 void amg_extract_level0(dp_sim* s) {
     Topo& t = s->topo;
     int nr = t.n + t.nw;
-    extract_ap_kernel<<<ceil_div(nr, 256), 256, 0, s->stream>>>(s->A, s->Ap0.rowptr, s->ap_src, t.fperf,
-                                                               t.n, nr, s->Ap0.val);
+    if (s->fp32)
+        extract_ap_kernel<float><<<ceil_div(nr, 256), 256, 0, s->stream>>>(s->A, s->Ap0.rowptr, s->ap_src, t.fperf,
+                                                                          t.n, nr, s->Ap0.val, (float*)s->st0);
+    else
+        extract_ap_kernel<double><<<ceil_div(nr, 256), 256, 0, s->stream>>>(s->A, s->Ap0.rowptr, s->ap_src, t.fperf,
+                                                                           t.n, nr, s->Ap0.val, (double*)s->st0);
     DP_LAUNCH_CHECK();
 }
 
@@ -1309,6 +1322,86 @@ static void op_launch(dp_sim* s, const Op& op, const T* dinv, const T* b, const 
     DP_LAUNCH_CHECK();
 }
 
+// Level 0 (the reduced pressure system) in stencil form: fracture row q takes
+// its six face neighbours (fcol; an absent face points at the row itself with
+// a zero value), its diagonal and, when perforated, its well, with values by
+// slot (st0, written with the CSR values at setup); well rows come from the
+// FP64 CSR, one workgroup each.  Same modes as the CSR kernels (PRE, POST).
+template <class T>
+struct St0Args {
+    const T* v;
+    const int* fcol;
+    const int* fperf;
+    const int* perf_well;
+    const int* rowptr;
+    const int* col;
+    const double* val;  // the FP64 CSR of level 0 (well rows), cast as the apply copies are
+    const T* dinv;
+    const T* b;
+    const T* x;
+    T* y;
+    T* y2;
+    int n;
+};
+
+template <class T, int MODE>
+__device__ inline T st0_x(const St0Args<T>& a, int c) {
+    return MODE == SV_PRE ? a.dinv[c] * a.b[c] : a.x[c];
+}
+
+template <class T, int MODE>
+__device__ inline void st0_store(const St0Args<T>& a, int r, T acc) {
+    if (MODE == SV_PRE) {
+        a.y[r] = a.dinv[r] * a.b[r];
+        a.y2[r] = a.b[r] - acc;
+    } else {
+        a.y[r] = a.x[r] + a.dinv[r] * (a.b[r] - acc);
+    }
+}
+
+template <class T, int MODE>
+__global__ void __launch_bounds__(256) st0_kernel(St0Args<T> a, int bf) {
+    __shared__ T sh[256 / WAVE];
+    const int b = blockIdx.x;
+    const int n = a.n;
+    if (b < bf) {
+        const int q = xcd_block(b, bf) * blockDim.x + threadIdx.x;
+        if (q >= n) return;
+        T acc = 0;
+#pragma unroll
+        for (int sl = 0; sl < 6; ++sl)
+            acc += a.v[(int64_t)sl * n + q] * st0_x<T, MODE>(a, a.fcol[(int64_t)sl * n + q] - n);
+        acc += a.v[(int64_t)6 * n + q] * st0_x<T, MODE>(a, q);
+        const int p = a.fperf[q];
+        if (p >= 0) acc += a.v[(int64_t)7 * n + q] * st0_x<T, MODE>(a, n + a.perf_well[p]);
+        st0_store<T, MODE>(a, q, acc);
+    } else {
+        const int r = n + (b - bf);
+        T acc = 0;
+        for (int e = a.rowptr[r] + (int)threadIdx.x; e < a.rowptr[r + 1]; e += blockDim.x)
+            acc += (T)a.val[e] * st0_x<T, MODE>(a, a.col[e]);
+        acc = wave_sum(acc);
+        if (threadIdx.x % WAVE == 0) sh[threadIdx.x / WAVE] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            T t = 0;
+            for (int i = 0; i < (int)(blockDim.x / WAVE); ++i) t += sh[i];
+            st0_store<T, MODE>(a, r, t);
+        }
+    }
+}
+
+template <class T, int MODE>
+static void st0_launch(dp_sim* s, const AmgLevel& lv, const T* dinv, const T* b, const T* x, T* y, T* y2) {
+    const Topo& t = s->topo;
+    if (lv.n != t.n + t.nw) throw Error(DP_E_INVALID, "level 0 is not the reduced pressure system");
+    St0Args<T> a{(const T*)s->st0, t.fcol, t.fperf, t.perf_well, lv.A.rowptr, lv.A.col, lv.A.val,
+                 dinv, b, x, y, y2, t.n};
+    const int bf = ceil_div(t.n, 256);
+    if (bf + t.nw > 0) st0_kernel<T, MODE><<<bf + t.nw, 256, 0, s->stream>>>(a, bf);
+    DP_LAUNCH_CHECK();
+}
+
 template <class T>
 T* amg_vcycle(dp_sim* s) {
     int L = (int)s->levels.size();
@@ -1317,7 +1410,7 @@ T* amg_vcycle(dp_sim* s) {
         AmgLevel& nx = s->levels[l + 1];
         // level 0 forms x = dinv b itself; the restriction into a smoothed
         // level forms it there (one gather per entry in the residual instead of two)
-        if (l == 0) op_launch<T, SV_PRE>(s, lv.Aop, (T*)lv.dinv, (T*)lv.b, nullptr, (T*)lv.x, (T*)lv.r);
+        if (l == 0) st0_launch<T, SV_PRE>(s, lv, (T*)lv.dinv, (T*)lv.b, nullptr, (T*)lv.x, (T*)lv.r);
         else op_launch<T, SV_RES>(s, lv.Aop, nullptr, (T*)lv.b, (T*)lv.x, (T*)lv.r, nullptr);
         if (l + 1 < L - 1) op_launch<T, SV_YD>(s, lv.Rop, (T*)nx.dinv, nullptr, (T*)lv.r, (T*)nx.b, (T*)nx.x);
         else op_launch<T, SV_Y>(s, lv.Rop, nullptr, nullptr, (T*)lv.r, (T*)nx.b, nullptr);
@@ -1332,7 +1425,8 @@ T* amg_vcycle(dp_sim* s) {
     for (int l = L - 2; l >= 0; --l) {
         AmgLevel& lv = s->levels[l];
         op_launch<T, SV_PROL>(s, lv.Pop, nullptr, nullptr, xs, (T*)lv.x, nullptr);
-        op_launch<T, SV_POST>(s, lv.Aop, (T*)lv.dinv, (T*)lv.b, (T*)lv.x, (T*)lv.t, nullptr);
+        if (l == 0) st0_launch<T, SV_POST>(s, lv, (T*)lv.dinv, (T*)lv.b, (T*)lv.x, (T*)lv.t, nullptr);
+        else op_launch<T, SV_POST>(s, lv.Aop, (T*)lv.dinv, (T*)lv.b, (T*)lv.x, (T*)lv.t, nullptr);
         xs = (T*)lv.t;
     }
     return xs;

@@ -203,6 +203,7 @@ struct dp_sim {
     // preconditioner work vectors (apply precision), [nb] 2-vectors
     void *pr = nullptr, *pz = nullptr, *pt = nullptr, *pz2 = nullptr;
     void* rpm = nullptr;  // [n] matrix-node pressure residuals of the current apply
+    void* st0 = nullptr;  // [8n] level-0 pressure operator of fracture row q by slot: faces 0..5, diagonal, well column
     // GMRES (FP64)
     double* V = nullptr;   // [(restart+1) * 2nb]
     double* Z = nullptr;   // [restart * 2nb]

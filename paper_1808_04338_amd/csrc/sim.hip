@@ -256,6 +256,7 @@ static Layout layout(dp_sim* s, Arena& a, const HostTopo& h) {
     s->pt = a.take(es * 2 * nb, "precond vectors");
     s->pz2 = a.take(es * 2 * nb, "precond vectors");
     s->rpm = a.take(es * (n > 0 ? n : 1), "precond vectors");
+    s->st0 = a.take(es * 8 * (n > 0 ? n : 1), "level-0 stencil");
     int m = s->restart;
     s->V = a.get<double>((int64_t)(m + 1) * 2 * nb, "krylov basis");
     s->Z = a.get<double>((int64_t)m * 2 * nb, "krylov basis");
