@@ -6,6 +6,11 @@
 
 namespace dp {
 
+// The calling thread's pinned host buffer of PINNED_SLOTS int64 (slot 0: scan
+// totals; slots 1..7 free for other small read-backs before a synchronisation).
+constexpr int PINNED_SLOTS = 8;
+int64_t* pinned_slots();
+
 int64_t scan_tmp_size(int64_t n);
 // In-place exclusive scan; returns the total (synchronises the stream).
 int64_t exclusive_scan(hipStream_t st, int64_t* data, int64_t n, int64_t* tmp, int64_t* host_total);

@@ -89,18 +89,31 @@ void scan_inplace(hipStream_t st, int64_t* data, int64_t n, int64_t* tmp) {
     if (n > 0) scan_rec(st, data, n, tmp);
 }
 
+// Small pinned host buffer of the calling thread, for results read back after
+// a synchronisation (a DMA into pinned memory instead of a staged pageable
+// copy).  Allocated on first use; held until the process ends.
+int64_t* pinned_slots() {
+    thread_local int64_t* p = nullptr;
+    if (!p) DP_HIP(hipHostMalloc((void**)&p, sizeof(int64_t) * PINNED_SLOTS, hipHostMallocDefault));
+    return p;
+}
+
+__global__ void scan_keep_last(const int64_t* data, int64_t n, int64_t* last) { *last = data[n - 1]; }
+__global__ void scan_total(const int64_t* data, int64_t n, int64_t* last) { *last += data[n - 1]; }
+
 int64_t exclusive_scan(hipStream_t st, int64_t* data, int64_t n, int64_t* tmp, int64_t* host_total) {
     if (n <= 0) return 0;
     // total = last prefix + last value: keep the last value before scanning
     int64_t* last_val = tmp;
-    DP_HIP(hipMemcpyAsync(last_val, data + n - 1, sizeof(int64_t), hipMemcpyDeviceToDevice, st));
+    scan_keep_last<<<1, 1, 0, st>>>(data, n, last_val);
     scan_rec(st, data, n, tmp + 1);
-    int64_t h[2];
-    DP_HIP(hipMemcpyAsync(&h[0], data + n - 1, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    DP_HIP(hipMemcpyAsync(&h[1], last_val, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    scan_total<<<1, 1, 0, st>>>(data, n, last_val);
+    DP_LAUNCH_CHECK();
+    int64_t* h = pinned_slots();
+    DP_HIP(hipMemcpyAsync(h, last_val, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     DP_HIP(hipStreamSynchronize(st));
-    if (host_total) *host_total = h[0] + h[1];
-    return h[0] + h[1];
+    if (host_total) *host_total = h[0];
+    return h[0];
 }
 
 // ---------------------------------------------------------------------------

@@ -501,8 +501,10 @@ static bool seg_run(hipStream_t st, const Src& S, const int64_t* off, int nrows,
             DP_LAUNCH_CHECK();
         }
         // the flags arrive with the scan's synchronisation
-        DP_HIP(hipMemcpyAsync(hf, flags, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
+        int* hfp = reinterpret_cast<int*>(pinned_slots() + 1);
+        DP_HIP(hipMemcpyAsync(hfp, flags, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
         exclusive_scan(st, cnt, nrows, tmp, &total);
+        for (int i = 0; i < 4; ++i) hf[i] = hfp[i];
         if (hf[2]) {
             if (!long_rows(st, S, longlist, hf[2], nrows, ncols, cnt, total, sc)) return false;
             if (long_products) *long_products += 1;

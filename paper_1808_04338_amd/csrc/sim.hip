@@ -425,7 +425,7 @@ static int gmres(dp_sim* s, double rtol, int maxit, int* iters, double* rel_res)
     double beta = bnorm;
     const double* rvec = b;
     int its = 0;
-    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), hbuf(64);
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
     while (beta > rtol * bnorm && its < maxit) {
         vec_scale_to(s, rvec, 1.0 / beta, s->V, len);
         std::fill(g.begin(), g.end(), 0.0);
@@ -454,8 +454,9 @@ static int gmres(dp_sim* s, double rtol, int maxit, int* iters, double* rel_res)
             else gs_finish_dot(s, s->V, len, j, hb + 32, inv_alpha, r, len, hb);
             // w' = w - V h into slot j + 1, a = V^T w' and |w'|^2 (at hb + 32)
             gs_update_dot_norm(s, s->V, len, j + 1, hb, r, s->V + (int64_t)(j + 1) * len, len, hb + 32);
-            DP_HIP(hipMemcpyAsync(hbuf.data(), hb, sizeof(double) * 64, hipMemcpyDeviceToHost, s->stream));
+            DP_HIP(hipMemcpyAsync(s->hpin, hb, sizeof(double) * 64, hipMemcpyDeviceToHost, s->stream));
             DP_HIP(hipStreamSynchronize(s->stream));
+            const double* hbuf = s->hpin;
             // column j: CGS2's coefficients h + a, and |w' - V a| by the
             // Pythagorean relation (V orthonormal)
             double n2 = hbuf[32 + j + 1], aa = 0.0;
@@ -976,6 +977,7 @@ dp_status sim_create(const dp_sim_desc* desc, const double* p0, const double* sw
         DP_HIP(hipEventCreate(&s->ev1));
         for (auto& pe : s->pev)
             for (auto& e : pe) DP_HIP(hipEventCreate(&e));
+        DP_HIP(hipHostMalloc((void**)&s->hpin, sizeof(double) * 64, hipHostMallocDefault));
         mark_old(s);
         DP_HIP(hipStreamSynchronize(st));
         sc.top = 0;
@@ -984,10 +986,12 @@ dp_status sim_create(const dp_sim_desc* desc, const double* p0, const double* sw
     } catch (const dp::Error& e) {
         g_create_error = e.what();
         dp_status c = e.code;
+        if (s->hpin) (void)hipHostFree(s->hpin);
         delete s;
         return c;
     } catch (const std::exception& e) {
         g_create_error = e.what();
+        if (s->hpin) (void)hipHostFree(s->hpin);
         delete s;
         return DP_E_DEVICE;
     }
@@ -1005,6 +1009,7 @@ dp_status sim_destroy(dp_sim* sim) {
             if (e) (void)hipEventDestroy(e);
     if (sim->pc_exec) (void)hipGraphExecDestroy(sim->pc_exec);
     if (sim->cap_stream) (void)hipStreamDestroy(sim->cap_stream);
+    if (sim->hpin) (void)hipHostFree(sim->hpin);
     delete sim;
     return DP_OK;
 }
