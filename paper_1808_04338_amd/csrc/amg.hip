@@ -858,13 +858,12 @@ static void build_op(dp_sim* s, const Csr& A, Op& op, bool pad_self, Arena& H, A
         sell_width<<<ceil_div(nsl + 1, 256), 256, 0, st>>>(A, nsl, w, dmax);
         DP_LAUNCH_CHECK();
         scan_inplace(st, w, nsl + 1, tmp);
-        int64_t h[2] = {0, 0};
+        int64_t* h = pinned_slots() + 1;
         DP_HIP(hipMemcpyAsync(&h[0], w + nsl, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-        int hm = 0;
-        DP_HIP(hipMemcpyAsync(&hm, dmax, sizeof(int), hipMemcpyDeviceToHost, st));
+        DP_HIP(hipMemcpyAsync(&h[1], dmax, sizeof(int), hipMemcpyDeviceToHost, st));
         DP_HIP(hipStreamSynchronize(st));
         total = h[0];
-        maxw = hm;
+        maxw = *reinterpret_cast<int*>(&h[1]);
     }
     bool sell = total <= (int64_t)(1.3 * (double)A.nnz) + 64 && maxw <= 48;
     size_t es = s->fp32 ? sizeof(float) : sizeof(double);
@@ -944,10 +943,10 @@ static void coarse_inverse(dp_sim* s, const Csr& A, Arena& H, Arena& Sc) {
         copy_inv<double><<<ceil_div((int64_t)n * n, 256), 256, 0, st>>>(M, np, n, (double*)s->coarse_inv);
     }
     DP_LAUNCH_CHECK();
-    int hbad = 0;
-    DP_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    int* hbad = reinterpret_cast<int*>(pinned_slots() + 1);
+    DP_HIP(hipMemcpyAsync(hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
     DP_HIP(hipStreamSynchronize(st));
-    if (hbad) fail(DP_E_NUMERIC, "zero pivot in the coarsest-level dense inverse");
+    if (*hbad) fail(DP_E_NUMERIC, "zero pivot in the coarsest-level dense inverse");
     Sc.top = mark;
 }
 
@@ -1002,10 +1001,10 @@ void amg_setup(dp_sim* s) {
                     pmis_fpass<<<rl_grid(n), 256, 0, st>>>(A, smask, state, iter, und + b);
                 }
                 DP_LAUNCH_CHECK();
-                int hu = 0;
-                DP_HIP(hipMemcpyAsync(&hu, und + PMIS_BATCH - 1, sizeof(int), hipMemcpyDeviceToHost, st));
+                int* hup = reinterpret_cast<int*>(pinned_slots() + 1);
+                DP_HIP(hipMemcpyAsync(hup, und + PMIS_BATCH - 1, sizeof(int), hipMemcpyDeviceToHost, st));
                 DP_HIP(hipStreamSynchronize(st));
-                if (hu == 0) break;
+                if (*hup == 0) break;
             }
             pmis_final<<<ceil_div(n, 256), 256, 0, st>>>(n, state, L.cf, cidx);
             DP_LAUNCH_CHECK();

@@ -479,8 +479,9 @@ ResNorm residual_norm(dp_sim* s, double dt) {
                                                 t.nw, dt, s->rho_o_ref, s->rho_w_ref, s->red_part);
     resnorm_final<<<1, 256, 0, s->stream>>>(s->red_part, nblk, s->red_out);
     DP_LAUNCH_CHECK();
-    DP_HIP(hipMemcpyAsync(s->red_host, s->red_out, 3 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    DP_HIP(hipMemcpyAsync(s->hpin, s->red_out, 3 * sizeof(double), hipMemcpyDeviceToHost, s->stream));
     DP_HIP(hipStreamSynchronize(s->stream));
+    for (int i = 0; i < 3; ++i) s->red_host[i] = s->hpin[i];
     ResNorm r;
     r.cnv = s->red_host[0];
     double pv = s->pore_volume > 0 ? s->pore_volume : 1.0;

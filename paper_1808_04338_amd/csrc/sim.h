@@ -211,7 +211,7 @@ struct dp_sim {
     double* red_part = nullptr;   // per-block partial sums
     double* red_out = nullptr;    // reduction results (device)
     double red_host[256] = {};    // host copy of reduction results
-    double* hpin = nullptr;        // [64] pinned host copy of the GMRES coefficients of one iteration
+    double* hpin = nullptr;        // [64] pinned host buffer of the small read-backs (GMRES coefficients, norms, sums)
     unsigned int* red_count = nullptr;
     int red_blocks = 0;
     int64_t seg_fallbacks = 0;  // AMG products that took the global sort path

@@ -413,9 +413,9 @@ static int gmres(dp_sim* s, double rtol, int maxit, int* iters, double* rel_res)
     double* hb = s->red_out;  // [0,32) h, [32,64) a and |w'|^2, [96] norms
     vec_zero(s, x, len);
     norm2(s, b, len, hb + 96);
-    double hn2 = 0;
-    DP_HIP(hipMemcpyAsync(&hn2, hb + 96, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+    DP_HIP(hipMemcpyAsync(s->hpin, hb + 96, sizeof(double), hipMemcpyDeviceToHost, s->stream));
     DP_HIP(hipStreamSynchronize(s->stream));
+    double hn2 = s->hpin[0];
     double bnorm = std::sqrt(hn2);
     *iters = 0;
     if (!(bnorm > 0)) {
@@ -500,8 +500,9 @@ static int gmres(dp_sim* s, double rtol, int maxit, int* iters, double* rel_res)
         combine(s, s->Z, len, k, y.data(), x, len);
         bresidual<double>(s, (const d2*)b, (const d2*)x, (d2*)r);
         norm2(s, r, len, hb + 96);
-        DP_HIP(hipMemcpyAsync(&hn2, hb + 96, sizeof(double), hipMemcpyDeviceToHost, s->stream));
+        DP_HIP(hipMemcpyAsync(s->hpin, hb + 96, sizeof(double), hipMemcpyDeviceToHost, s->stream));
         DP_HIP(hipStreamSynchronize(s->stream));
+        hn2 = s->hpin[0];
         beta = std::sqrt(hn2);
         rvec = r;
         if (!std::isfinite(beta)) {
@@ -580,8 +581,9 @@ static void mass_sums(dp_sim* s, double out[6]) {
     DP_LAUNCH_CHECK();
     mass_sums_final<<<1, 64, 0, s->stream>>>(s->red_part, nblk, s->red_out + 128);
     DP_LAUNCH_CHECK();
-    DP_HIP(hipMemcpyAsync(out, s->red_out + 128, sizeof(double) * 6, hipMemcpyDeviceToHost, s->stream));
+    DP_HIP(hipMemcpyAsync(s->hpin, s->red_out + 128, sizeof(double) * 6, hipMemcpyDeviceToHost, s->stream));
     DP_HIP(hipStreamSynchronize(s->stream));
+    for (int i = 0; i < 6; ++i) out[i] = s->hpin[i];
 }
 
 static void copy_state(dp_sim* s, const d2* from, d2* to) {
