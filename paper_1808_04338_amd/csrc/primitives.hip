@@ -73,16 +73,18 @@ int64_t scan_tmp_size(int64_t n) {
     return tot + 2;
 }
 
-static void scan_rec(hipStream_t st, int64_t* data, int64_t n, int64_t* tmp) {
+// Returns the device address that holds the sum of all n values: the tile sum
+// written by the single tile of the deepest level.
+static int64_t* scan_rec(hipStream_t st, int64_t* data, int64_t n, int64_t* tmp) {
     int nblk = ceil_div(n, SCAN_TILE);
     int64_t* sums = tmp;
     scan_tiles<<<nblk, SCAN_T, 0, st>>>(data, n, sums);
     DP_LAUNCH_CHECK();
-    if (nblk > 1) {
-        scan_rec(st, sums, nblk, tmp + nblk + 1);
-        scan_add<<<nblk, SCAN_T, 0, st>>>(data, n, sums);
-        DP_LAUNCH_CHECK();
-    }
+    if (nblk == 1) return sums;
+    int64_t* total = scan_rec(st, sums, nblk, tmp + nblk + 1);
+    scan_add<<<nblk, SCAN_T, 0, st>>>(data, n, sums);
+    DP_LAUNCH_CHECK();
+    return total;
 }
 
 void scan_inplace(hipStream_t st, int64_t* data, int64_t n, int64_t* tmp) {
@@ -98,19 +100,11 @@ int64_t* pinned_slots() {
     return p;
 }
 
-__global__ void scan_keep_last(const int64_t* data, int64_t n, int64_t* last) { *last = data[n - 1]; }
-__global__ void scan_total(const int64_t* data, int64_t n, int64_t* last) { *last += data[n - 1]; }
-
 int64_t exclusive_scan(hipStream_t st, int64_t* data, int64_t n, int64_t* tmp, int64_t* host_total) {
     if (n <= 0) return 0;
-    // total = last prefix + last value: keep the last value before scanning
-    int64_t* last_val = tmp;
-    scan_keep_last<<<1, 1, 0, st>>>(data, n, last_val);
-    scan_rec(st, data, n, tmp + 1);
-    scan_total<<<1, 1, 0, st>>>(data, n, last_val);
-    DP_LAUNCH_CHECK();
+    const int64_t* total = scan_rec(st, data, n, tmp + 1);
     int64_t* h = pinned_slots();
-    DP_HIP(hipMemcpyAsync(h, last_val, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    DP_HIP(hipMemcpyAsync(h, total, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     DP_HIP(hipStreamSynchronize(st));
     if (host_total) *host_total = h[0];
     return h[0];
