@@ -774,11 +774,17 @@ __global__ void __launch_bounds__(256) gj_row(double* M, int np, int kb, const d
 }
 
 // All tiles (i, j) with i != k: M_ij -= C_i M_kj (j != k), M_ik = -C_i P.
-// Tile (k, k) becomes P.
+// Tile (k, k) becomes P.  Look-ahead (Pn given): block 0 takes tile
+// (k+1, k+1), the next diagonal block, and once it is updated inverts it into
+// Pn exactly as gj_diag would, while the other blocks update the rest.
 __global__ void __launch_bounds__(256) gj_update(double* M, int np, int kb, const double* __restrict__ P,
-                                                 const double* __restrict__ Cbuf) {
+                                                 const double* __restrict__ Cbuf, double* Pn, int* bad) {
+    __shared__ double tl[GJ_B][GJ_B + 1];
     int nbk = np / GJ_B;
-    int ib = blockIdx.x / nbk, jb = blockIdx.x % nbk;
+    const int la = Pn ? (kb + 1) * nbk + (kb + 1) : -1;
+    int t = blockIdx.x;
+    if (la >= 0) t = t == 0 ? la : (t <= la ? t - 1 : t);
+    int ib = t / nbk, jb = t % nbk;
     int wv = threadIdx.x / WAVE;
     int qr = wv / 2, qc = wv % 2;
     double* T = M + (int64_t)ib * GJ_B * np + jb * GJ_B;
@@ -804,19 +810,41 @@ __global__ void __launch_bounds__(256) gj_update(double* M, int np, int kb, cons
         for (int i = 0; i < 4; ++i) {
             int r, c;
             tile_rc(i, qr, qc, r, c);
-            T[(int64_t)r * np + c] -= acc[i];
+            const double v = T[(int64_t)r * np + c] - acc[i];
+            T[(int64_t)r * np + c] = v;
+            if (t == la) tl[r][c] = v;
+        }
+        if (t == la) {
+            __syncthreads();
+            if (wv == 0) {
+                const int j = threadIdx.x;
+                double a[GJ_B];
+#pragma unroll
+                for (int r = 0; r < GJ_B; ++r) a[r] = j < GJ_B ? tl[r][j] : (r == j - GJ_B ? 1.0 : 0.0);
+                gj_steps<0>(a, bad);
+                if (j >= GJ_B) {
+#pragma unroll
+                    for (int r = 0; r < GJ_B; ++r) Pn[r * GJ_B + (j - GJ_B)] = a[r];
+                }
+            }
         }
     }
 }
 
 // In-place inverse of the np x np row-major matrix M (np a multiple of 32).
-// P: 32x32 scratch, C: np x 32 scratch, bad: set to 1 on a zero pivot.
+// P: 2 x 32x32 scratch (the pivot blocks of even and odd panels), C: np x 32
+// scratch, bad: set to 1 on a zero pivot.  Only the first diagonal block has a
+// launch of its own; each later one is inverted inside the previous panel's
+// update.
 void gj_invert(hipStream_t st, double* M, int np, double* P, double* C, int* bad) {
     int nbk = np / GJ_B;
+    if (nbk == 0) return;
+    gj_diag<<<1, 64, 0, st>>>(M, np, 0, P, bad);
     for (int kb = 0; kb < nbk; ++kb) {
-        gj_diag<<<1, 64, 0, st>>>(M, np, kb, P, bad);
-        gj_row<<<2 * nbk, 256, 0, st>>>(M, np, kb, P, C);
-        gj_update<<<nbk * nbk, 256, 0, st>>>(M, np, kb, P, C);
+        double* Pk = P + (kb & 1) * GJ_B * GJ_B;
+        double* Pn = kb + 1 < nbk ? P + ((kb + 1) & 1) * GJ_B * GJ_B : nullptr;
+        gj_row<<<2 * nbk, 256, 0, st>>>(M, np, kb, Pk, C);
+        gj_update<<<nbk * nbk, 256, 0, st>>>(M, np, kb, Pk, C, Pn, bad);
     }
     DP_LAUNCH_CHECK();
 }
@@ -928,7 +956,7 @@ static void coarse_inverse(dp_sim* s, const Csr& A, Arena& H, Arena& Sc) {
     int np = ((n + GJ_B - 1) / GJ_B) * GJ_B;
     size_t mark = Sc.top;
     double* M = Sc.get<double>((int64_t)np * np, "coarse dense");
-    double* P = Sc.get<double>(GJ_B * GJ_B, "coarse pivot block");
+    double* P = Sc.get<double>(2 * GJ_B * GJ_B, "coarse pivot blocks");
     double* C = Sc.get<double>((int64_t)np * GJ_B, "coarse column panel");
     int* bad = Sc.get<int>(1, "coarse flag");
     DP_HIP(hipMemsetAsync(bad, 0, sizeof(int), st));
@@ -1449,7 +1477,7 @@ extern "C" dp_status dp_selftest_dense_inverse(const double* a, int32_t n, doubl
         ar.base = (char*)d_ws;
         ar.cap = bytes;
         double* M = ar.get<double>((int64_t)np * np, "dense matrix");
-        double* P = ar.get<double>(GJ_B * GJ_B, "pivot block");
+        double* P = ar.get<double>(2 * GJ_B * GJ_B, "pivot blocks");
         double* C = ar.get<double>((int64_t)np * GJ_B, "column panel");
         int* bad = ar.get<int>(1, "flag");
         std::vector<double> h((size_t)np * np, 0.0);
