@@ -195,9 +195,14 @@ dp_status assemble_residual_jacobian(dp_sim *sim, double dt, double *res_scaled)
 dp_status cpr_fpf_setup(dp_sim *sim);
 
 /* GMRES(restart) on the decoupled system D^-1 J y = -D^-1 R with CPR-FPF (right
- * preconditioning) from y = 0, to ||b - A y|| <= rtol ||b||.  The correction
- * stays on the device for newton_update.  Returns DP_E_NOCONV (keeping the
- * best iterate) if maxit is reached. */
+ * preconditioning) from y = 0, to ||b - A y|| <= rtol ||b|| (Sec. 3.2).  The
+ * Arnoldi columns are those of classical Gram-Schmidt with one
+ * re-orthogonalisation pass; the correction and normalisation of each new
+ * basis vector are applied in the next iteration's first pass over the basis,
+ * two passes per iteration.  One host synchronisation per iteration (the
+ * Givens rotations run on the host).  The correction stays on the device for
+ * newton_update.  Returns DP_E_NOCONV (keeping the best iterate) if maxit is
+ * reached. */
 dp_status krylov_solve(dp_sim *sim, double rtol, int32_t maxit, int32_t *iters,
                        double *rel_res);
 
