@@ -93,14 +93,20 @@ def test_decoupling_and_ilu_match_oracle(name):
     sim.close()
 
 
-@pytest.mark.parametrize("name", ["medium", "tall_well"])
+@pytest.mark.parametrize("name", ["medium", "tall_well", "no_wells"])
 def test_amg_hierarchy_matches_oracle(name):
     """Identical C/F splittings at every level (a deterministic rule), P and the
-    Galerkin operators to 1e-10: on the 144k-DOF model, and on a 6x6x900 model
+    Galerkin operators to 1e-10: on the 144k-DOF model; on a 6x6x900 model
     whose two wells perforate 900 layers, so that Galerkin rows of every length
     class occur (wavefront tiles, workgroup tiles and rows beyond the LDS tiles,
-    which take the global sort path)."""
-    m = synth.model_layered() if name == "medium" else synth.model_tiny(6, 6, 900, seed=6)
+    which take the global sort path); and on a 40x40x6 model without wells,
+    whose level 0 has no well rows for the stencil form of the V-cycle."""
+    if name == "medium":
+        m = synth.model_layered()
+    elif name == "tall_well":
+        m = synth.model_tiny(6, 6, 900, seed=6)
+    else:
+        m = synth.model_tiny(40, 40, 6, seed=8, wells=False)
     x, x_old = random_state_pair(m, 5)
     dt = 5 * synth.DAY
     geo, R, J = oracle_system(m, x, x_old, dt)
