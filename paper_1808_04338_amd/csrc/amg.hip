@@ -396,6 +396,11 @@ __device__ inline bool better(double aw, int ac, double bw, int bc) {
     return fa > fb || (fa == fb && ac < bc);
 }
 
+// The trunc best entries of W's row i (best first), the row sum and the count
+// of non-zero entries.  Each entry is inserted where the sequential insertion
+// would put it: pos = the number of kept entries that stay ahead of it (the
+// kept list is sorted, so "better" holds from pos on).  Every array index is a
+// compile-time constant, so the selection stays in registers.
 __device__ inline void select_row(const Csr& W, int i, double d, int trunc, Sel& sel, double& total,
                                   int& nnzw) {
     sel.n = 0;
@@ -407,17 +412,25 @@ __device__ inline void select_row(const Csr& W, int i, double d, int trunc, Sel&
         ++nnzw;
         total += w;
         int c = W.col[e];
-        // insertion into the sorted selection
-        int pos = sel.n;
-        while (pos > 0 && better(w, c, sel.w[pos - 1], sel.col[pos - 1])) --pos;
+        int pos = 0;
+#pragma unroll
+        for (int t = 0; t < TRUNC_MAX; ++t)
+            if (t < sel.n && !better(w, c, sel.w[t], sel.col[t])) ++pos;
         if (pos < trunc) {
-            int last = sel.n < trunc ? sel.n : trunc - 1;
-            for (int t = last; t > pos; --t) {
-                sel.w[t] = sel.w[t - 1];
-                sel.col[t] = sel.col[t - 1];
+#pragma unroll
+            for (int t = TRUNC_MAX - 1; t > 0; --t) {
+                if (t > pos && t <= sel.n && t < trunc) {
+                    sel.w[t] = sel.w[t - 1];
+                    sel.col[t] = sel.col[t - 1];
+                }
             }
-            sel.w[pos] = w;
-            sel.col[pos] = c;
+#pragma unroll
+            for (int t = 0; t < TRUNC_MAX; ++t) {
+                if (t == pos) {
+                    sel.w[t] = w;
+                    sel.col[t] = c;
+                }
+            }
             if (sel.n < trunc) ++sel.n;
         }
     }
@@ -462,22 +475,33 @@ __global__ void pfill_kernel(Csr W, const int* __restrict__ cf, const int64_t* _
     double scale = 1.0;
     if (nnzw > trunc) {
         double kept = 0.0;
-        for (int t = 0; t < sel.n; ++t) kept += sel.w[t];
+#pragma unroll
+        for (int t = 0; t < TRUNC_MAX; ++t)
+            if (t < sel.n) kept += sel.w[t];
         scale = kept != 0.0 ? total / kept : 1.0;
     }
-    // kept entries in column order
-    for (int a = 1; a < sel.n; ++a)
-        for (int b = a; b > 0 && sel.col[b] < sel.col[b - 1]; --b) {
-            int tc = sel.col[b];
-            sel.col[b] = sel.col[b - 1];
-            sel.col[b - 1] = tc;
-            double tw = sel.w[b];
-            sel.w[b] = sel.w[b - 1];
-            sel.w[b - 1] = tw;
+    // kept entries in column order (columns are distinct; an exchange network
+    // with compile-time indices)
+#pragma unroll
+    for (int p = 0; p < TRUNC_MAX - 1; ++p) {
+#pragma unroll
+        for (int b = 0; b < TRUNC_MAX - 1 - p; ++b) {
+            if (b + 1 < sel.n && sel.col[b + 1] < sel.col[b]) {
+                int tc = sel.col[b];
+                sel.col[b] = sel.col[b + 1];
+                sel.col[b + 1] = tc;
+                double tw = sel.w[b];
+                sel.w[b] = sel.w[b + 1];
+                sel.w[b + 1] = tw;
+            }
         }
-    for (int t = 0; t < sel.n; ++t) {
-        pcol[o + t] = sel.col[t];
-        pval[o + t] = nnzw > trunc ? sel.w[t] * scale : sel.w[t];
+    }
+#pragma unroll
+    for (int t = 0; t < TRUNC_MAX; ++t) {
+        if (t < sel.n) {
+            pcol[o + t] = sel.col[t];
+            pval[o + t] = nnzw > trunc ? sel.w[t] * scale : sel.w[t];
+        }
     }
 }
 
