@@ -228,9 +228,16 @@ __global__ void zero_kernel(double* x, int64_t len) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < len) x[i] = 0.0;
 }
+// Elementwise casts take two elements per thread (16-byte FP64 and 8-byte FP32
+// accesses; the arrays start 256-byte aligned); an odd last element alone.
 __global__ void f32_kernel(const double* __restrict__ x, double a, float* y, int64_t len) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < len) y[i] = (float)(a * x[i]);
+    int64_t e = 2 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+    if (e + 1 < len) {
+        double2 v = *reinterpret_cast<const double2*>(x + e);
+        *reinterpret_cast<float2*>(y + e) = make_float2((float)(a * v.x), (float)(a * v.y));
+    } else if (e < len) {
+        y[e] = (float)(a * x[e]);
+    }
 }
 __global__ void f64_kernel(const float* __restrict__ x, double* y, int64_t len) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -238,8 +245,14 @@ __global__ void f64_kernel(const float* __restrict__ x, double* y, int64_t len) 
 }
 __global__ void add_f64_kernel(const float* __restrict__ a, const float* __restrict__ b, double* y,
                                int64_t len) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < len) y[i] = (double)(a[i] + b[i]);
+    int64_t e = 2 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+    if (e + 1 < len) {
+        float2 u = *reinterpret_cast<const float2*>(a + e);
+        float2 v = *reinterpret_cast<const float2*>(b + e);
+        *reinterpret_cast<double2*>(y + e) = make_double2((double)(u.x + v.x), (double)(u.y + v.y));
+    } else if (e < len) {
+        y[e] = (double)(a[e] + b[e]);
+    }
 }
 template <class T>
 __global__ void add3_kernel(const T* __restrict__ a, const T* __restrict__ b, T* y, int64_t len) {
@@ -287,7 +300,7 @@ void vec_axpy(dp_sim* s, double alpha, const double* x, double* y, int64_t len) 
     DP_LAUNCH_CHECK();
 }
 void to_f32(dp_sim* s, const double* x, float* y, int64_t len, double a) {
-    f32_kernel<<<ceil_div(len, 256), 256, 0, s->stream>>>(x, a, y, len);
+    f32_kernel<<<ceil_div((len + 1) / 2, 256), 256, 0, s->stream>>>(x, a, y, len);
     DP_LAUNCH_CHECK();
 }
 void to_f64(dp_sim* s, const float* x, double* y, int64_t len) {
@@ -295,7 +308,7 @@ void to_f64(dp_sim* s, const float* x, double* y, int64_t len) {
     DP_LAUNCH_CHECK();
 }
 void add_to_f64(dp_sim* s, const float* a, const float* b, double* y, int64_t len) {
-    add_f64_kernel<<<ceil_div(len, 256), 256, 0, s->stream>>>(a, b, y, len);
+    add_f64_kernel<<<ceil_div((len + 1) / 2, 256), 256, 0, s->stream>>>(a, b, y, len);
     DP_LAUNCH_CHECK();
 }
 template <class T>
