@@ -1288,8 +1288,19 @@ __global__ void __launch_bounds__(256) dense_gemv(const T* __restrict__ M, int n
     int row = blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
     int lane = threadIdx.x % WAVE;
     if (row >= n) return;
+    // four loads in flight per lane, summed in the same order as one at a time
+    const T* m = M + (int64_t)row * n;
     T acc = 0;
-    for (int c = lane; c < n; c += WAVE) acc += M[(int64_t)row * n + c] * b[c];
+    int c = lane;
+    for (; c + 3 * WAVE < n; c += 4 * WAVE) {
+        const T m0 = m[c], m1 = m[c + WAVE], m2 = m[c + 2 * WAVE], m3 = m[c + 3 * WAVE];
+        const T b0 = b[c], b1 = b[c + WAVE], b2 = b[c + 2 * WAVE], b3 = b[c + 3 * WAVE];
+        acc += m0 * b0;
+        acc += m1 * b1;
+        acc += m2 * b2;
+        acc += m3 * b3;
+    }
+    for (; c < n; c += WAVE) acc += m[c] * b[c];
     acc = wave_sum(acc);
     if (lane == 0) y[row] = acc;
 }
