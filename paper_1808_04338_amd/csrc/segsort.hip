@@ -271,12 +271,20 @@ __global__ void __launch_bounds__(256) seg_block(Src S, const int* __restrict__ 
 __global__ void __launch_bounds__(WAVE) seg_copy(const int64_t* __restrict__ off, const int* __restrict__ rowptr,
                                                  int nrows, int G, const int* __restrict__ col,
                                                  const double* __restrict__ val, int* ocol, double* oval) {
+    // the group's row offsets (G <= SEG_GMAX) in LDS for the per-entry row search
+    __shared__ int rp[SEG_GMAX + 1];
+    __shared__ int64_t ro[SEG_GMAX];
     int r0 = blockIdx.x * G;
     int r1 = min(r0 + G, nrows);
-    int o0 = rowptr[r0], o1 = rowptr[r1];
+    for (int i = threadIdx.x; i <= r1 - r0; i += WAVE) {
+        rp[i] = rowptr[r0 + i];
+        if (i < r1 - r0) ro[i] = off[r0 + i];
+    }
+    __syncthreads();
+    int o0 = rp[0], o1 = rp[r1 - r0];
     for (int o = o0 + (int)threadIdx.x; o < o1; o += WAVE) {
-        int r = r0 + upper_idx(rowptr + r0, r1 - r0, o);
-        int64_t src = off[r] + (o - rowptr[r]);
+        int rl = upper_idx(rp, r1 - r0, o);
+        int64_t src = ro[rl] + (o - rp[rl]);
         ocol[o] = col[src];
         oval[o] = val[src];
     }
