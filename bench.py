@@ -31,8 +31,8 @@ HBM_PEAK_GBS = 8000.0
 # the figures were taken on the 60x220x85 model in the FP32-preconditioner form
 # and are reported only for it, and only while that source is unchanged.
 TRAFFIC = {
-    "amg_rowwise_products": dict(bytes=377.5e6, source="paper_1808_04338_amd/csrc/segsort.hip",
-                                 sha256="80664f648aa6e1f5"),
+    "amg_rowwise_products": dict(bytes=378.0e6, source="paper_1808_04338_amd/csrc/segsort.hip",
+                                 sha256="9fdca8883cf4dceb"),
     "block_ilu0_solve": dict(bytes=273.0e6, source="paper_1808_04338_amd/csrc/linalg.hip",
                              sha256="308ad367d9068634"),
 }
