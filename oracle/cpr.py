@@ -28,11 +28,8 @@ Readings of what the paper leaves open:
   W = -D^-1 (A^s_FC + A^s_FF B^-1 Abar^s_FC), truncated to 3 entries per row
   (row sum kept); Galerkin coarse operators R A P with R = P^T; l1-Jacobi
   smoothing; coarsest level solved exactly.
-* GMRES: right-preconditioned, restart 30, classical Gram-Schmidt with one
-  re-orthogonalisation pass, Givens rotations; the tolerance is on the
-  decoupled residual.  The re-orthogonalisation correction and the
-  normalisation of each new basis vector are deferred to the next iteration
-  (see gmres), which leaves the Hessenberg columns those of CGS2.
+* GMRES: right-preconditioned, restart 30, classical Gram-Schmidt applied
+  twice (CGS2), Givens rotations; the tolerance is on the decoupled residual.
 """
 import numpy as np
 import scipy.sparse as sp
@@ -269,15 +266,16 @@ def pmis(A, smask):
     return state
 
 
-def interpolation(A, smask, state, trunc=4):
+def interpolation(A, smask, state, trunc=3):
     """Extended (distance-two) interpolation in matrix-product form, truncated.
 
     For an F point i with strong C set C_i, strong F set F_i and weak set W_i:
       abar_kj = a_kj if j in C_k and a_kj a_kk < 0 (else 0), beta_k = sum_j abar_kj
       d_i  = a_ii + sum_{n in W_i} a_in + sum_{k in F_i, beta_k = 0} a_ik
       w_ij = -(1/d_i) [ a_ij [j in C_i] + sum_{k in F_i, beta_k != 0} a_ik abar_kj / beta_k ]
-    then the 4 largest |w_ij| are kept (ties: lower coarse index) and scaled so
-    the row sum is unchanged.  C points interpolate by injection.
+    then the ``trunc`` largest |w_ij| are kept (3 by default, as in the AMG
+    hierarchy; ties: lower coarse index) and scaled so the row sum is
+    unchanged.  C points interpolate by injection.
     """
     A, n, rows, cols, v = _csr_parts(A)
     isC = state == 1
@@ -460,25 +458,24 @@ class CPRFPF:
 
 
 def gmres(matvec, precond, b, rtol, restart=30, maxit=300, x0=None, trace=None):
-    """Right-preconditioned restarted GMRES with CGS2 Arnoldi and Givens
+    """Right-preconditioned restarted GMRES (Sec. 3.2; Saad and Schultz's
+    GMRES(m)) with classical Gram-Schmidt applied twice (CGS2) and Givens
     rotations.  Returns (x, iterations, relative true residual).
 
-    Iteration j projects w = A z_j on the orthonormal basis v_0..v_j
-    (h = V^T w, w' = w - V h) and measures what is left (a = V^T w',
-    n2 = |w'|^2).  Column j of the Hessenberg matrix is h + a with
-    subdiagonal alpha = sqrt(n2 - |a|^2): the coefficients and the norm of
-    classical Gram-Schmidt with one re-orthogonalisation pass, the norm by the
-    Pythagorean relation (V orthonormal).  The corrected vector
-    v_{j+1} = (w' - V a) / alpha is formed at the start of the next iteration,
-    together with that iteration's projections, and the preconditioner of
-    iteration j+1 is applied to w' scaled to unit length:
-    z_{j+1} = M^-1 (w' / sqrt(n2)).  The relation A Z = V H holds for the
-    stored Z whichever vector z_{j+1} was made from, so the least-squares step
-    is that of GMRES; span(Z) differs from the Krylov space of the v's only by
-    the rounding-size a.
+    Iteration j, textbook order:
+      z_j = M^-1 v_j;  w = A z_j;
+      h1 = V^T w,  w <- w - V h1   (first classical Gram-Schmidt pass);
+      h2 = V^T w,  w <- w - V h2   (second pass, the re-orthogonalisation);
+      H[:j+1, j] = h1 + h2,  H[j+1, j] = |w|,  v_{j+1} = w / |w|;
+    then the rotations of the earlier columns are applied to column j, a new
+    rotation zeroes H[j+1, j], and |g_{j+1}| is the residual norm of the
+    least-squares iterate.  At the end of a cycle y solves the triangular
+    system R y = g and x <- x + Z y (right preconditioning: the iterate is
+    x0 + M^-1 V y).  The loop stops when |g_{j+1}| <= rtol |b| (x0 = 0) or
+    after maxit iterations; each restart starts from the true residual.
 
-    If ``trace`` is a dict, the first cycle's V (its last vector formed), Z
-    and (unrotated) Hessenberg matrix are stored in it."""
+    If ``trace`` is a dict, the first cycle's V, Z and (unrotated) Hessenberg
+    matrix are stored in it."""
     n = b.shape[0]
     x = np.zeros(n) if x0 is None else x0.copy()
     bnorm = np.linalg.norm(b)
@@ -497,25 +494,21 @@ def gmres(matvec, precond, b, rtol, restart=30, maxit=300, x0=None, trace=None):
         g = np.zeros(restart + 1)
         g[0] = beta
         V[0] = r / beta
-        pending = V[0]          # the vector the next preconditioner step takes
-        scale = 1.0             # ... scaled by this
-        a_prev, alpha_prev = None, 1.0
         k = 0
         for j in range(restart):
-            Z[j] = precond(pending * scale)
+            Z[j] = precond(V[j])
             w = matvec(Z[j])
-            if j > 0:
-                V[j] = (pending - V[:j].T @ a_prev) / alpha_prev
-            h = V[:j + 1] @ w
-            w = w - V[:j + 1].T @ h
-            a = V[:j + 1] @ w
-            n2 = w @ w
-            d = n2 - a @ a
-            hn = np.sqrt(d) if d > 0.0 else 0.0
+            h1 = V[:j + 1] @ w
+            w = w - V[:j + 1].T @ h1
+            h2 = V[:j + 1] @ w
+            w = w - V[:j + 1].T @ h2
+            hn = np.linalg.norm(w)
             col = np.zeros(restart + 1)
-            col[:j + 1] = h + a
+            col[:j + 1] = h1 + h2
             col[j + 1] = hn
             Hraw[:, j] = col
+            if hn > 0.0:
+                V[j + 1] = w / hn
             for i in range(j):
                 t = cs[i] * col[i] + sn[i] * col[i + 1]
                 col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1]
@@ -530,12 +523,9 @@ def gmres(matvec, precond, b, rtol, restart=30, maxit=300, x0=None, trace=None):
             H[:, j] = col
             its += 1
             k = j + 1
-            pending, a_prev, alpha_prev = w, a, hn
-            scale = 1.0 / np.sqrt(n2) if n2 > 0.0 else 0.0
             if hn == 0.0 or abs(g[j + 1]) <= rtol * bnorm or its >= maxit:
                 break
         if trace is not None and "V" not in trace:
-            V[k] = (pending - V[:k].T @ a_prev) / alpha_prev if alpha_prev != 0.0 else 0.0
             trace.update(V=V[:k + 1].copy(), Z=Z[:k].copy(), H=Hraw[:k + 1, :k].copy())
         y = np.linalg.solve(np.triu(H[:k, :k]), g[:k])
         x = x + Z[:k].T @ y
