@@ -146,6 +146,11 @@ typedef struct {
                                  use the one-by-one path) [0] */
     int32_t decoupling;       /* DP_DEC_GJ | DP_DEC_ABF | DP_DEC_TI [DP_DEC_GJ] */
     int32_t cpr_variant;      /* DP_CPR_FPF | DP_CPR_FP [DP_CPR_FPF] */
+    int32_t newton_stall;     /* stagnation exit of a sub-step's Newton loop, when > 0: the
+                                 sub-step fails (and is cut) once this many iterations in a row
+                                 have not lowered the smallest CNV of its updated iterates
+                                 (iterations 1, 2, ...; iteration 0 is the start state); 0 or
+                                 less leaves max_newton as the only limit [off] */
 } dp_sim_desc;
 
 typedef struct {

@@ -15,7 +15,10 @@ relative-permeability end points it would cross, and clamps S_w to [0, 1];
 BHP-controlled wells have p_b pinned to the target after every update;
 convergence is the scaled max-norm (CNV) together with the material-balance
 measure (MB) below; at most ``max_newton``
-iterations, then the step is cut in half (at most ``max_cuts`` times).  After a
+iterations, then the step is cut in half (at most ``max_cuts`` times).  The
+sub-step also fails early when ``stall`` iterations in a row have not lowered
+the smallest CNV its updated iterates have reached (a stagnating or
+oscillating Newton iteration; off unless ``stall`` > 0).  After a
 converged step a rate injector whose p_b exceeds its limit switches to BHP
 control at the limit and the step is repeated (at most once per step).
 """
@@ -120,14 +123,18 @@ def forcing_term(choice, eta_prev, nb, nb_prev, nr_prev, nd, gamma=0.9, beta=2.0
 
 def newton_solve(geo, x0, acc_old, dt, control, tol=1e-10, max_newton=20,
                  linear="lu", eta=1e-10, cpr_opts=None, mb_tol=1e-7, forcing=0, eta0=0.1,
-                 forcing_opts=None):
+                 forcing_opts=None, stall=0):
     """Newton iterations from x0.  Converged when the scaled max-norm (CNV) is at
-    most tol and the material-balance measure at most mb_tol.  With forcing 1-3
+    most tol and the material-balance measure at most mb_tol.  Not converged
+    after max_newton iterations, or when ``stall`` iterations in a row have not
+    gone below the smallest CNV of the earlier updated iterates (iterations
+    1..l-1; iteration 0 is the start state, the previous step's solution).  With forcing 1-3
     the first linear tolerance is eta0 and the later ones follow Eq. (13).
     Returns (x, converged, iterations, info); info["eta"] lists the tolerances."""
     x = x0.copy()
     info = {"res": [], "lin_iters": [], "eta": []}
     prev = None  # (eta, ||b||, ||r||, r) of the previous iteration
+    best, best_it = np.inf, 0  # smallest CNV so far and the iteration that reached it
     for it in range(max_newton + 1):
         R = ph.residual(geo, x, acc_old, dt, control)
         nrm = scaled_residual_norm(geo, R, dt, control)
@@ -138,6 +145,11 @@ def newton_solve(geo, x0, acc_old, dt, control, tol=1e-10, max_newton=20,
             return x, True, it, info
         if it == max_newton:
             break
+        if it >= 1:  # only iterates produced by an update count (x0 solved the previous step)
+            if nrm < best:
+                best, best_it = nrm, it
+            elif stall > 0 and it - best_it >= stall:
+                return x, False, it, info
         J = ph.jacobian(geo, x, dt, control)
         b = -R
         if forcing:

@@ -1,6 +1,8 @@
 // Device primitives used by the AMG setup: exclusive scan of int64 counts and a
 // stable LSD radix sort of (64-bit key, double) pairs, plus reduce-by-key into
 // CSR.  All are deterministic.
+#include <mutex>
+#include <vector>
 #include "primitives.h"
 
 namespace dp {
@@ -93,11 +95,36 @@ void scan_inplace(hipStream_t st, int64_t* data, int64_t n, int64_t* tmp) {
 
 // Small pinned host buffer of the calling thread, for results read back after
 // a synchronisation (a DMA into pinned memory instead of a staged pageable
-// copy).  Allocated on first use; held until the process ends.
+// copy).  A thread takes a buffer from a shared free list (or allocates one)
+// on first use and returns it to the list when it exits, so the pinned memory
+// held is bounded by the largest number of threads that ran setups at once.
+namespace {
+std::mutex g_pin_mu;
+std::vector<int64_t*> g_pin_free;
+struct PinHolder {
+    int64_t* p = nullptr;
+    ~PinHolder() {
+        if (p) {
+            std::lock_guard<std::mutex> g(g_pin_mu);
+            g_pin_free.push_back(p);
+        }
+    }
+};
+}  // namespace
+
 int64_t* pinned_slots() {
-    thread_local int64_t* p = nullptr;
-    if (!p) DP_HIP(hipHostMalloc((void**)&p, sizeof(int64_t) * PINNED_SLOTS, hipHostMallocDefault));
-    return p;
+    thread_local PinHolder h;
+    if (!h.p) {
+        {
+            std::lock_guard<std::mutex> g(g_pin_mu);
+            if (!g_pin_free.empty()) {
+                h.p = g_pin_free.back();
+                g_pin_free.pop_back();
+            }
+        }
+        if (!h.p) DP_HIP(hipHostMalloc((void**)&h.p, sizeof(int64_t) * PINNED_SLOTS, hipHostMallocDefault));
+    }
+    return h.p;
 }
 
 int64_t exclusive_scan(hipStream_t st, int64_t* data, int64_t n, int64_t* tmp, int64_t* host_total) {

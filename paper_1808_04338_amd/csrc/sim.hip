@@ -658,12 +658,26 @@ static bool newton_loop(dp_sim* s, double h, int* newton_its, int* lin_its, doub
     // previous iteration's eta, ||b||, ||r|| (b = -R; r = b - J y, stored negated in ft)
     bool have_prev = false;
     double eta_prev = 0, nb_prev = 0, nr_prev = 0;
+    // stagnation exit: the smallest CNV of this sub-step's updated iterates and the
+    // iteration that reached it
+    double best = INFINITY;
+    int best_it = 0;
     for (int it = 0; it <= d.max_newton; ++it) {
         ResNorm nrm = assemble(s, h);
         *res_out = nrm.cnv;
         if (!finite(nrm)) return false;
         if (converged(s, nrm)) return true;
         if (it == d.max_newton) break;
+        // the residual of the start state (iteration 0) belongs to the previous step's
+        // solution; the exit judges only the iterates Newton has produced
+        if (it >= 1) {
+            if (nrm.cnv < best) {
+                best = nrm.cnv;
+                best_it = it;
+            } else if (d.newton_stall > 0 && it - best_it >= d.newton_stall) {
+                return false;
+            }
+        }
         double eta = d.lin_rtol, nb = 0, nd = 0;
         if (d.forcing) {
             nb = dev_norm(s, (const double*)s->res);
@@ -709,13 +723,11 @@ static bool newton_loop(dp_sim* s, double h, int* newton_its, int* lin_its, doub
     return false;
 }
 
-static int do_timestep(dp_sim* s, double dt, dp_step_info* info) {
+static int timestep_body(dp_sim* s, double dt, dp_step_info* info, const std::vector<int>& ctrl0) {
     const dp_sim_desc& d = s->desc;
     s->eta_hist.clear();
     dp_step_info out{};
-    std::vector<int> ctrl0 = host_ctrl(s);
     std::vector<int> ctrl = ctrl0;
-    copy_state(s, s->x, s->x_save);
     // state at the start of the current sub-step (device copy, for retries)
     copy_state(s, s->x, s->x_sub);
     double remaining = dt, h = dt;
@@ -778,6 +790,28 @@ static int do_timestep(dp_sim* s, double dt, dp_step_info* info) {
     out.cuts = cuts;
     if (info) *info = out;
     return DP_OK;
+}
+
+// A timestep that fails, by non-convergence or by an error thrown anywhere in
+// it (a workspace region overflowing in the setup, a failed HIP call), leaves
+// the state and the well controls of the start of the step, with no work of
+// the step still queued on the stream.
+static int do_timestep(dp_sim* s, double dt, dp_step_info* info) {
+    std::vector<int> ctrl0 = host_ctrl(s);
+    copy_state(s, s->x, s->x_save);
+    try {
+        return timestep_body(s, dt, info, ctrl0);
+    } catch (...) {
+        try {
+            copy_state(s, s->x_save, s->x);
+            set_controls(s, ctrl0);
+            DP_HIP(hipStreamSynchronize(s->stream));
+        } catch (...) {
+            (void)hipStreamSynchronize(s->stream);
+        }
+        s->stage = 0;
+        throw;
+    }
 }
 
 double kernel_bytes(dp_sim* s, int kernel) {
@@ -1001,6 +1035,8 @@ dp_status sim_create(const dp_sim_desc* desc, const double* p0, const double* sw
 
 dp_status sim_destroy(dp_sim* sim) {
     if (!sim) return DP_OK;
+    // no kernel of this handle may still write the workspace once the caller frees it
+    (void)hipStreamSynchronize(sim->stream);
     if (sim->ev0) (void)hipEventDestroy(sim->ev0);
     if (sim->ev1) (void)hipEventDestroy(sim->ev1);
     for (auto& pe : sim->pev)

@@ -83,6 +83,7 @@ def make_desc(model, precision=None, **opts):
     d.precond_eager = int(opts.get("precond_eager", 0))
     d.decoupling = {"gj": 0, "abf": 1, "ti": 2}[opts.get("decoupling", "gj")]
     d.cpr_variant = {"fpf": 0, "fp": 1}[opts.get("cpr_variant", "fpf")]
+    d.newton_stall = int(opts.get("newton_stall", 0))
     return d, keep
 
 
@@ -113,6 +114,10 @@ class Sim:
         base = self.workspace.data_ptr()
         aligned = (base + 255) & ~255
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        if self.stream != torch.cuda.current_stream(self.device):
+            # the library works on self.stream: the caching allocator must not hand this
+            # block to another stream's allocation before that stream's work is done
+            self.workspace.record_stream(self.stream)
         p0 = np.ascontiguousarray(model["p0"], dtype=np.float64)
         sw0 = np.ascontiguousarray(model["sw0"], dtype=np.float64)
         h = C.c_void_p()

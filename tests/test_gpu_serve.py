@@ -22,14 +22,22 @@ def test_alone_equals_mix_bitwise():
 
     a = _req(0, 0, (20, 20, 10), 0.0)
     alone, _ = serve([a], keep_state=True)
+    # request 4 has 1,008,010 unknowns: its preconditioner runs kernel by kernel,
+    # the small models' from their captured graphs
+    big = (60, 60, 70)
     mix = [_req(0, 0, (20, 20, 10), 0.0), _req(1, 1, (40, 40, 10), 0.0),
-           _req(2, 2, (20, 20, 10), 0.01), _req(3, 3, (60, 60, 10), 0.02)]
+           _req(2, 2, (20, 20, 10), 0.01), _req(3, 3, (60, 60, 10), 0.02),
+           _req(4, 4, big, 0.0, steps=2)]
     res, summ = serve(mix, keep_state=True)
-    assert summ["completed"] == 4 and summ["peak_active"] >= 2
+    assert summ["completed"] == 5 and summ["peak_active"] >= 2
+    assert res[4].state[0].shape[0] == 2 * 60 * 60 * 70
     for u, v in zip(alone[0].state, res[0].state):
         assert np.array_equal(u, v)
     c_alone, _ = serve([_req(2, 2, (20, 20, 10), 0.0)], keep_state=True)
     for u, v in zip(c_alone[2].state, res[2].state):
+        assert np.array_equal(u, v)
+    big_alone, _ = serve([_req(4, 4, big, 0.0, steps=2)], keep_state=True)
+    for u, v in zip(big_alone[4].state, res[4].state):
         assert np.array_equal(u, v)
 
 
