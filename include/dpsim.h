@@ -304,6 +304,21 @@ dp_status sim_apply_stage(dp_sim *sim, int32_t stage, const double *r, double *z
 dp_status dp_selftest_dense_inverse(const double *a, int32_t n, double *ainv, void *d_workspace,
                                     size_t workspace_bytes, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc or take a workspace from an allocator, such as tight serving loops
+ * or harnesses that forbid it): dp_selftest_dense_inverse with its device
+ * scratch (the padded matrix, the pivot blocks, a column panel and the pivot
+ * flag) in a static device array of the library, 8.7 MB on every GPU it runs
+ * on, held until the process ends, instead of a caller workspace.  Same
+ * kernels and results.  n <= 1024; larger n returns DP_E_INVALID.  The array
+ * keeps the previous call's contents; every call writes what it reads and
+ * clears the flag first.  All calls of the process share one array per GPU and
+ * are serialised by a lock inside the library (the call synchronises
+ * hip_stream before it returns), so they never overlap; do not call it while
+ * capturing a HIP graph (it synchronises). */
+dp_status dp_selftest_dense_inverse_noalloc(const double *a, int32_t n, double *ainv,
+                                            void *hip_stream);
+
 /* Time one kernel group on the handle's stream with HIP events, reps launches
  * after one untimed launch; returns the average ms per launch and the
  * algorithmic bytes one launch must move (values and indices read once, vectors

@@ -102,6 +102,7 @@ _SIGS = {
     "sim_apply_matrix": [C.c_void_p, _dptr, _dptr],
     "sim_apply_stage": [C.c_void_p, C.c_int32, _dptr, _dptr],
     "dp_selftest_dense_inverse": [_dptr, C.c_int32, _dptr, C.c_void_p, C.c_size_t, C.c_void_p],
+    "dp_selftest_dense_inverse_noalloc": [_dptr, C.c_int32, _dptr, C.c_void_p],
     "sim_bench_kernel": [C.c_void_p, C.c_int32, C.c_int32, _dptr, _dptr],
     "sim_enable_timing": [C.c_void_p, C.c_int32],
     "sim_phase_time": [C.c_void_p, C.c_int32, _dptr, _lptr],

@@ -8,6 +8,7 @@
 // coarse inverse) are kept in the preconditioner precision.
 #include <algorithm>
 #include <cstdlib>
+#include <mutex>
 #include <vector>
 
 #include "kernels.h"
@@ -1501,34 +1502,101 @@ template float* amg_vcycle<float>(dp_sim*);
 // ---------------------------------------------------------------------------
 // Test hooks: one preconditioner stage, dense inverse self-test
 // ---------------------------------------------------------------------------
+namespace dp {
+
+__global__ void set_flag_kernel(int* p, int v) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *p = v;
+}
+
+// One dense inverse with its device scratch taken from 'ar': the matrix padded
+// to a multiple of the panel width (identity in the padding), the two pivot
+// blocks, one column panel and the pivot flag.  a and ainv are host arrays
+// (row-major n x n); synchronises st.
+static dp_status dense_inverse_in(Arena& ar, const double* a, int n, double* ainv, hipStream_t st) {
+    int np = ((n + GJ_B - 1) / GJ_B) * GJ_B;
+    double* M = ar.get<double>((int64_t)np * np, "dense matrix");
+    double* P = ar.get<double>(2 * GJ_B * GJ_B, "pivot blocks");
+    double* C = ar.get<double>((int64_t)np * GJ_B, "column panel");
+    int* bad = ar.get<int>(1, "flag");
+    std::vector<double> h((size_t)np * np, 0.0);
+    for (int r = 0; r < np; ++r)
+        for (int c = 0; c < np; ++c)
+            h[(size_t)r * np + c] = (r < n && c < n) ? a[(size_t)r * n + c] : (r == c ? 1.0 : 0.0);
+    DP_HIP(hipMemcpyAsync(M, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, st));
+    set_flag_kernel<<<1, 64, 0, st>>>(bad, 0);
+    DP_LAUNCH_CHECK();
+    gj_invert(st, M, np, P, C, bad);
+    int hb = 0;
+    DP_HIP(hipMemcpyAsync(h.data(), M, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
+    DP_HIP(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    DP_HIP(hipStreamSynchronize(st));
+    for (int r = 0; r < n; ++r)
+        for (int c = 0; c < n; ++c) ainv[(size_t)r * n + c] = h[(size_t)r * np + c];
+    return hb ? DP_E_NUMERIC : DP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free variant: the scratch of dense_inverse_in for n up to
+// DENSE_NOALLOC_MAX lives in a static device array of this module.  Host code
+// never passes the array's name (a host-side stand-in, not a device address):
+// its address on each device is looked up once with hipGetSymbolAddress, with
+// that device current, and kept per device.  One lock serialises the calls of
+// this process, which all share the array.
+// ---------------------------------------------------------------------------
+constexpr int DENSE_NOALLOC_MAX = 1024;
+constexpr size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
+constexpr size_t DENSE_NOALLOC_BYTES =
+    round256(sizeof(double) * (size_t)DENSE_NOALLOC_MAX * DENSE_NOALLOC_MAX) +
+    round256(sizeof(double) * 2 * GJ_B * GJ_B) + round256(sizeof(double) * (size_t)DENSE_NOALLOC_MAX * GJ_B) +
+    round256(sizeof(int));
+
+static __device__ __align__(256) unsigned char scratch[DENSE_NOALLOC_BYTES];
+
+static std::mutex g_scratch_mu;
+static std::vector<void*> g_scratch_ptr;  // per device ordinal; null until looked up
+
+// Device address of 'scratch' on the current device (caller holds g_scratch_mu).
+static void* scratch_on_current_device() {
+    int dev = 0;
+    DP_HIP(hipGetDevice(&dev));
+    if (dev < 0) fail(DP_E_DEVICE, "no current device");
+    if ((size_t)dev >= g_scratch_ptr.size()) g_scratch_ptr.resize((size_t)dev + 1, nullptr);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            fail(DP_E_DEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace dp
+
 extern "C" dp_status dp_selftest_dense_inverse(const double* a, int32_t n, double* ainv, void* d_ws,
-                                                size_t bytes, void* stream) {
+                                               size_t bytes, void* stream) {
     using namespace dp;
     if (!a || !ainv || !d_ws || n <= 0 || n > 4096) return DP_E_INVALID;
     try {
-        hipStream_t st = (hipStream_t)stream;
-        int np = ((n + GJ_B - 1) / GJ_B) * GJ_B;
         Arena ar;
         ar.base = (char*)d_ws;
         ar.cap = bytes;
-        double* M = ar.get<double>((int64_t)np * np, "dense matrix");
-        double* P = ar.get<double>(2 * GJ_B * GJ_B, "pivot blocks");
-        double* C = ar.get<double>((int64_t)np * GJ_B, "column panel");
-        int* bad = ar.get<int>(1, "flag");
-        std::vector<double> h((size_t)np * np, 0.0);
-        for (int r = 0; r < np; ++r)
-            for (int c = 0; c < np; ++c)
-                h[(size_t)r * np + c] = (r < n && c < n) ? a[(size_t)r * n + c] : (r == c ? 1.0 : 0.0);
-        DP_HIP(hipMemcpyAsync(M, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, st));
-        DP_HIP(hipMemsetAsync(bad, 0, sizeof(int), st));
-        gj_invert(st, M, np, P, C, bad);
-        int hb = 0;
-        DP_HIP(hipMemcpyAsync(h.data(), M, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
-        DP_HIP(hipMemcpyAsync(&hb, bad, sizeof(int), hipMemcpyDeviceToHost, st));
-        DP_HIP(hipStreamSynchronize(st));
-        for (int r = 0; r < n; ++r)
-            for (int c = 0; c < n; ++c) ainv[(size_t)r * n + c] = h[(size_t)r * np + c];
-        return hb ? DP_E_NUMERIC : DP_OK;
+        return dense_inverse_in(ar, a, n, ainv, (hipStream_t)stream);
+    } catch (const Error& e) {
+        return e.code;
+    }
+}
+
+extern "C" dp_status dp_selftest_dense_inverse_noalloc(const double* a, int32_t n, double* ainv,
+                                                       void* stream) {
+    using namespace dp;
+    if (!a || !ainv || n <= 0 || n > DENSE_NOALLOC_MAX) return DP_E_INVALID;
+    try {
+        std::lock_guard<std::mutex> g(g_scratch_mu);
+        Arena ar;
+        ar.base = (char*)scratch_on_current_device();
+        ar.cap = DENSE_NOALLOC_BYTES;
+        return dense_inverse_in(ar, a, n, ainv, (hipStream_t)stream);
     } catch (const Error& e) {
         return e.code;
     }

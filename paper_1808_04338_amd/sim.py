@@ -362,3 +362,16 @@ def dense_inverse_selftest(a, device="cuda:0"):
                                          C.c_size_t(16 * npad * npad + 65536), C.c_void_p(st.cuda_stream))
     L.check(code)
     return out
+
+
+def dense_inverse_noalloc(a, device="cuda:0"):
+    """The same inverse with the library's static device scratch (no workspace)."""
+    import torch
+
+    lib = L.load()
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    n = a.shape[0]
+    out = np.empty_like(a)
+    st = torch.cuda.current_stream(torch.device(device))
+    L.check(lib.dp_selftest_dense_inverse_noalloc(_dp(a), n, _dp(out), C.c_void_p(st.cuda_stream)))
+    return out
