@@ -335,7 +335,9 @@ dp_status sim_bench_kernel(dp_sim *sim, int32_t kernel, int32_t reps, double *av
  * to 1024 launches) and adds the launch's algorithmic bytes.  kernel: 0 FP64
  * block SpMV of the decoupled matrix in GMRES; 1 block ILU(0) solve (its four
  * kernels as one launch); 2 row-wise AMG products A P and R (A P) (wavefront
- * tiles and the two workgroup tiers as one launch).  on != 0 resets and
+ * tiles and the two workgroup tiers as one launch); 3 AMG V-cycle of the
+ * pressure stage (all its levels as one launch; not timed while the
+ * preconditioner replays from its graph).  on != 0 resets and
  * starts, 0 stops.  sim_kernel_time synchronises the stream and returns the
  * summed device time (ms), the number of timed launches and the summed bytes. */
 dp_status sim_kernel_timer(dp_sim *sim, int32_t kernel, int32_t on);

@@ -37,7 +37,12 @@ static void apply_core(dp_sim* s, const V2<T>* r) {
     if (s->desc.cpr_variant == DP_CPR_FP) vec_fill_zero<T>(s, (T*)z1, 2 * (int64_t)s->topo.nb);
     else ilu_solve<T>(s, r, z1);
     bresidual_p<T>(s, r, z1, (T*)s->levels[0].b);
-    T* e = amg_vcycle<T>(s);
+    T* e;
+    {
+        KtScope ks(s->capturing ? nullptr : &s->kt[3], s->stream);
+        e = amg_vcycle<T>(s);
+        ks.bytes(kernel_bytes(s, 2));
+    }
     bresidual_prol<T>(s, r, z1, e, z2, t);
     ilu_solve<T>(s, t, z1);
 }

@@ -117,7 +117,8 @@ struct PhaseTimer {
 // stream (up to KT_CAP launches; the events are read when the timer is queried)
 // and its algorithmic bytes are added up.
 constexpr int KT_CAP = 1024;
-constexpr int KT_N = 3;  // 0 FP64 block SpMV, 1 block ILU(0) solve, 2 row-wise AMG products
+constexpr int KT_N = 4;  // 0 FP64 block SpMV, 1 block ILU(0) solve, 2 row-wise AMG products,
+                         // 3 AMG V-cycle
 struct KernelTimer {
     bool on = false;
     int used = 0;
