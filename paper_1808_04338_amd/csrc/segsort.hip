@@ -78,6 +78,52 @@ struct ProdSrc {
     double* oval;
 };
 
+// The bitonic network over KPL * WAVE keys of one wavefront, in registers:
+// element e = KPL * lane + i sits in register i of its lane.  Stages with a
+// distance j below KPL compare registers of one lane; the others exchange the
+// same register with lane ^ (j / KPL).  Element e keeps the minimum of its pair
+// when (e is the lower of the pair) == (the pair sorts ascending, e & k == 0),
+// exactly the compare-exchange of the LDS network.
+template <int KPL>
+__device__ inline void wave_bitonic(uint64_t* key) {
+    const int lane = threadIdx.x % WAVE;
+    constexpr int N = KPL * WAVE;
+    uint64_t v[KPL];
+#pragma unroll
+    for (int i = 0; i < KPL; ++i) v[i] = key[KPL * lane + i];
+#pragma unroll
+    for (int k = 2; k <= N; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            if (j < KPL) {
+#pragma unroll
+                for (int i = 0; i < KPL; ++i) {
+                    if ((i & j) == 0) {
+                        const int l = i | j;
+                        const bool up = ((KPL * lane + i) & k) == 0;
+                        const uint64_t a = v[i], b = v[l];
+                        const uint64_t mn = a < b ? a : b, mx = a < b ? b : a;
+                        v[i] = up ? mn : mx;
+                        v[l] = up ? mx : mn;
+                    }
+                }
+            } else {
+                const int lj = j / KPL;
+                const bool lower = (lane & lj) == 0;
+#pragma unroll
+                for (int i = 0; i < KPL; ++i) {
+                    const uint64_t o = __shfl_xor(v[i], lj, WAVE);
+                    const bool up = ((KPL * lane + i) & k) == 0;
+                    const uint64_t mn = v[i] < o ? v[i] : o, mx = v[i] < o ? o : v[i];
+                    v[i] = (lower == up) ? mn : mx;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < KPL; ++i) key[KPL * lane + i] = v[i];
+}
+
 template <int NT, int MAXE, class Src>
 __device__ void tile_run(SegTile<MAXE>& T, const Src& S, int ra, int rb, int64_t* cnt) {
     constexpr int IB = MAXE > 2048 ? 12 : (MAXE > 512 ? 11 : 9);  // bits of the term index (t < MAXE)
@@ -148,20 +194,27 @@ __device__ void tile_run(SegTile<MAXE>& T, const Src& S, int ra, int rb, int64_t
         }
     }
     __syncthreads();
-    // bitonic network, ascending
-    for (int k = 2; k <= P2; k <<= 1) {
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int p = tid; p < (P2 >> 1); p += NT) {
-                int i = ((p & ~(j - 1)) << 1) | (p & (j - 1));
-                int l = i + j;
-                bool up = (i & k) == 0;
-                uint64_t a = T.key[i], b = T.key[l];
-                if ((a > b) == up) {
-                    T.key[i] = b;
-                    T.key[l] = a;
+    // bitonic network, ascending: in registers for a one-wavefront tile, in LDS
+    // for a workgroup tile (the keys are unique, so both give the same order)
+    if constexpr (NT == WAVE && MAXE <= 4 * WAVE) {
+        if (P2 <= 2 * WAVE) wave_bitonic<2>(T.key);
+        else wave_bitonic<4>(T.key);
+        __syncthreads();
+    } else {
+        for (int k = 2; k <= P2; k <<= 1) {
+            for (int j = k >> 1; j > 0; j >>= 1) {
+                for (int p = tid; p < (P2 >> 1); p += NT) {
+                    int i = ((p & ~(j - 1)) << 1) | (p & (j - 1));
+                    int l = i + j;
+                    bool up = (i & k) == 0;
+                    uint64_t a = T.key[i], b = T.key[l];
+                    if ((a > b) == up) {
+                        T.key[i] = b;
+                        T.key[l] = a;
+                    }
                 }
+                __syncthreads();
             }
-            __syncthreads();
         }
     }
     // run sums at the heads, in term order within each run; a head's sum goes to
