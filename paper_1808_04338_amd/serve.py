@@ -108,7 +108,10 @@ def serve(requests, budget_bytes=200 << 30, max_active=64, precision="fp32", dev
         t = now()
         while pending and pending[0].arrival <= t:
             waiting.append(pending.popleft())
-        admitted_any = False
+        # admission under the lock only reserves memory and a slot; the handles
+        # (device allocation, upload, setup of the topology) are made outside it,
+        # so finishing workers never wait behind another model's creation
+        admitted = []
         with lock:
             while waiting and state["active"] < max_active:
                 req = waiting[0]
@@ -128,20 +131,24 @@ def serve(requests, budget_bytes=200 << 30, max_active=64, precision="fp32", dev
                 state["peak_active"] = max(state["peak_active"], state["active"])
                 state["peak_used"] = max(state["peak_used"], state["used"])
                 results[req.rid].admitted = now()
-                try:
-                    sim = sim_factory(req.model)
-                except L.DpError as e:
-                    results[req.rid].status = "failed"
-                    results[req.rid].error = str(e)
-                    results[req.rid].finished = now()
+                admitted.append((req, fp))
+        for req, fp in admitted:
+            try:
+                sim = sim_factory(req.model)
+            except L.DpError as e:
+                results[req.rid].status = "failed"
+                results[req.rid].error = str(e)
+                results[req.rid].finished = now()
+                with lock:
                     state["used"] -= fp
                     state["active"] -= 1
-                    continue
-                th = threading.Thread(target=worker, args=(req, sim, fp), daemon=True)
-                threads.append(th)
-                th.start()
-                admitted_any = True
-            if not admitted_any:
+                    lock.notify_all()
+                continue
+            th = threading.Thread(target=worker, args=(req, sim, fp), daemon=True)
+            threads.append(th)
+            th.start()
+        if not admitted:
+            with lock:
                 # sleep until the next arrival or until a model frees memory
                 timeout = None
                 if pending:
