@@ -322,9 +322,13 @@ def precision_deviation(model, jset, k, rtol):
     return out
 
 
+SERVED_MAX_LARGE = 4  # resident requests above 4 GiB (the 4.49M-DOF class)
+
+
 def served_leg(count):
     """Poisson arrivals (4/s), sizes uniform over five classes, 10 five-day steps
-    each, FP32 preconditioner, admission against a 200 GB budget."""
+    each, FP32 preconditioner, admission against a 200 GB budget with at most
+    SERVED_MAX_LARGE requests above 4 GiB resident at once."""
     import synth
     from paper_1808_04338_amd import Request, serve
 
@@ -341,8 +345,10 @@ def served_leg(count):
         log("served %d/%d finished: request %d (%s), %d steps, %s" % (k, len(reqs), r.rid, r.tag,
                                                                       len(r.latencies), r.status))
 
-    res, summ = serve(reqs, budget_bytes=200 << 30, precision="fp32", on_done=on_done)
+    res, summ = serve(reqs, budget_bytes=200 << 30, precision="fp32", on_done=on_done,
+                      max_large=SERVED_MAX_LARGE, large_bytes=4 << 30)
     summ["unit"] = "timesteps/s"
+    summ["admission"] = "FIFO by footprint, 200 GiB, at most %d resident requests above 4 GiB" % SERVED_MAX_LARGE
     summ["failures"] = [{"rid": r.rid, "class": r.tag, "steps_done": len(r.latencies),
                          "error": r.error} for r in res.values() if r.status != "ok"]
     return summ

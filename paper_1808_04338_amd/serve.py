@@ -47,12 +47,15 @@ class Result:
 
 def serve(requests, budget_bytes=200 << 30, max_active=64, precision="fp32", device="cuda:0",
           keep_state=False, clock=time.perf_counter, sim_factory=None, footprint_fn=None, on_done=None,
-          **sim_opts):
+          max_large=None, large_bytes=4 << 30, **sim_opts):
     """Run the requests; returns (results by rid, summary dict).
 
     sim_factory(model) -> handle and footprint_fn(model) -> bytes default to the
     library's Sim on its own stream and sim_footprint.  on_done(result), if
-    given, is called from the request's worker thread when it finishes."""
+    given, is called from the request's worker thread when it finishes.
+    max_large, if given, caps the resident requests whose footprint exceeds
+    large_bytes; a waiting request that fits may then be admitted ahead of a
+    large one held back by the cap."""
     if sim_factory is None:
         import torch
 
@@ -69,7 +72,7 @@ def serve(requests, budget_bytes=200 << 30, max_active=64, precision="fp32", dev
     pending = collections.deque(reqs)
     waiting = collections.deque()
     lock = threading.Condition()
-    state = {"used": 0, "active": 0, "peak_active": 0, "peak_used": 0}
+    state = {"used": 0, "active": 0, "peak_active": 0, "peak_used": 0, "large": 0}
     fps = {}
     threads = []
     t0 = clock()
@@ -100,6 +103,8 @@ def serve(requests, budget_bytes=200 << 30, max_active=64, precision="fp32", dev
             with lock:
                 state["used"] -= fp
                 state["active"] -= 1
+                if fp > large_bytes:
+                    state["large"] -= 1
                 lock.notify_all()
             if on_done is not None:
                 on_done(res)
@@ -113,21 +118,27 @@ def serve(requests, budget_bytes=200 << 30, max_active=64, precision="fp32", dev
         # so finishing workers never wait behind another model's creation
         admitted = []
         with lock:
-            while waiting and state["active"] < max_active:
-                req = waiting[0]
+            i = 0
+            while i < len(waiting) and state["active"] < max_active:
+                req = waiting[i]
                 if req.rid not in fps:
                     fps[req.rid] = footprint_fn(req.model)
                 fp = fps[req.rid]
                 if fp > budget_bytes:
-                    waiting.popleft()
+                    del waiting[i]
                     results[req.rid].status = "rejected"
                     results[req.rid].error = "footprint %d exceeds the budget" % fp
                     continue
+                large = fp > large_bytes
+                if large and max_large is not None and state["large"] >= max_large:
+                    i += 1  # held back by the cap: later requests may pass it
+                    continue
                 if state["used"] + fp > budget_bytes:
                     break
-                waiting.popleft()
+                del waiting[i]
                 state["used"] += fp
                 state["active"] += 1
+                state["large"] += 1 if large else 0
                 state["peak_active"] = max(state["peak_active"], state["active"])
                 state["peak_used"] = max(state["peak_used"], state["used"])
                 results[req.rid].admitted = now()
@@ -142,6 +153,8 @@ def serve(requests, budget_bytes=200 << 30, max_active=64, precision="fp32", dev
                 with lock:
                     state["used"] -= fp
                     state["active"] -= 1
+                    if fp > large_bytes:
+                        state["large"] -= 1
                     lock.notify_all()
                 continue
             th = threading.Thread(target=worker, args=(req, sim, fp), daemon=True)

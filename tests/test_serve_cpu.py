@@ -78,3 +78,38 @@ def test_completion_hook_runs_once_per_served_request():
                       footprint_fn=lambda m: m["fp"], on_done=on_done)
     assert sorted(seen) == [(i, 3, "ok") for i in range(6)]
     assert res[6].status == "rejected"
+
+
+def test_large_request_cap_lets_small_requests_pass():
+    """With max_large = 1, at most one request above large_bytes is resident at
+    a time, and a small request that arrives behind a held-back large one is
+    admitted before it."""
+    FakeSim.live = FakeSim.peak = 0
+    live_large = [0]
+    peak_large = [0]
+    lock = threading.Lock()
+
+    class CountingSim(FakeSim):
+        def __init__(self, model):
+            super().__init__(model)
+            if model["fp"] > 5:
+                with lock:
+                    live_large[0] += 1
+                    peak_large[0] = max(peak_large[0], live_large[0])
+
+        def close(self):
+            if self.model["fp"] > 5:
+                with lock:
+                    live_large[0] -= 1
+            super().close()
+
+    fps = [8, 8, 1, 8, 1]
+    reqs = [Request(i, _model("m%d" % i, fp, 3 if fp > 5 else 1), arrival=0.0001 * i, tag=fp)
+            for i, fp in enumerate(fps)]
+    res, summ = serve(reqs, budget_bytes=100, max_active=8, sim_factory=CountingSim,
+                      footprint_fn=lambda m: m["fp"], max_large=1, large_bytes=5)
+    assert summ["completed"] == len(reqs)
+    assert peak_large[0] == 1
+    # request 2 (small) arrived after request 1 (large, held back) and got in first
+    assert res[2].admitted < res[1].admitted
+    assert res[4].admitted < res[3].admitted
