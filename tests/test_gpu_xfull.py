@@ -73,12 +73,19 @@ def test_full_assembly(full):
     assert _row_err(Jg, full["J"]) <= 1e-12
 
 
-def test_full_decoupling_and_true_residual(full):
+@pytest.fixture(scope="module")
+def decoupled(full):
+    """The oracle's decoupled system D^-1 J, D^-1 (-R) at the full-size state."""
     geo, J, R = full["geo"], full["J"], full["R"]
-    Ag, bg = full["sim"].export_system(1)
     indptr, indices, data = oph.to_bsr(geo, J)
     dh, bh = ocpr.decouple(2 * geo.n, indptr, indices, data, -R)
-    Ah = oph.bsr_to_csr(indptr, indices, dh)
+    return oph.bsr_to_csr(indptr, indices, dh), bh
+
+
+def test_full_decoupling_and_true_residual(full, decoupled):
+    geo, J, R = full["geo"], full["J"], full["R"]
+    Ag, bg = full["sim"].export_system(1)
+    Ah, bh = decoupled
     # first node rows are judged against the magnitudes the Gauss-Jordan step
     # combined: |J_0j| + |a01/a11| |J_1j|
     nb = geo.N // 2
@@ -113,6 +120,18 @@ def full64(full):
     sim.setup()
     yield sim
     sim.close()
+
+
+def test_full_fp64_form_solves_to_its_tolerance(full, full64, decoupled):
+    """The plain FP64 form on the same Jacobian: GMRES reaches 1e-6 and its
+    solution's decoupled residual, recomputed by the oracle, is within it."""
+    Ah, bh = decoupled
+    its, rel = full64.solve(1e-6, 300)
+    y = full64.get_correction()
+    rel_o = np.linalg.norm(bh - Ah @ y) / np.linalg.norm(bh)
+    print("FP64 form: %d GMRES iterations, rel %.3e (oracle %.3e)" % (its, rel, rel_o))
+    assert rel <= 1e-6
+    assert rel_o <= 1.001e-6
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
