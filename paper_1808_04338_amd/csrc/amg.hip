@@ -891,9 +891,29 @@ __global__ void cast_vals(const double* __restrict__ a, int64_t n, T* b) {
     if (i < n) b[i] = (T)a[i];
 }
 
+// Row blocks of a CSR operator for the blocked apply: block k starts at the
+// first row whose entry offset reaches k * chunk, so with chunk = CSRS_CAP -
+// (longest row) its entries end before (k + 1) * chunk + (longest row), and the
+// last block ends at nnz <= nb * chunk: every block holds at most CSRS_CAP
+// entries.  desc[k] = (first row, its entry offset); desc[nb] = (n, nnz).  Each
+// k in [1, nb) has exactly one row r with rowptr[r-1] < k * chunk <= rowptr[r].
+constexpr int CSRS_NT = 256, CSRS_K = 4, CSRS_CAP = CSRS_NT * CSRS_K;
+
+__global__ void csrs_desc(const int* __restrict__ rowptr, int n, int64_t chunk, int nb, int2* desc) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r > n) return;
+    if (r == 0) desc[0] = make_int2(0, rowptr[0]);
+    if (r == n) desc[nb] = make_int2(n, rowptr[n]);
+    if (r == 0) return;
+    const int64_t lo = rowptr[r - 1], hi = rowptr[r];
+    for (int64_t k = lo / chunk + 1; k * chunk <= hi && k < nb; ++k) desc[k] = make_int2(r, (int)hi);
+}
+
 // Choose and build the apply form of a CSR operator.  SELL-64 when it pads by
-// at most 30% and no row is longer than 48, otherwise CSR with G lanes per row
-// (G the power of two at or above the mean row length, 4..64).
+// at most 30% and no row is longer than 48; otherwise row blocks of at most
+// CSRS_CAP entries when no row is longer than half of that, with 4 lanes per
+// row in the sums (8 from a mean of 32 entries per row); otherwise CSR with G
+// lanes per row (G the power of two at or above the mean row length, 4..64).
 static void build_op(dp_sim* s, const Csr& A, Op& op, bool pad_self, Arena& H, Arena& Sc,
                      const char* what) {
     hipStream_t st = s->stream;
@@ -937,15 +957,25 @@ static void build_op(dp_sim* s, const Csr& A, Op& op, bool pad_self, Arena& H, A
             DP_LAUNCH_CHECK();
         }
     } else {
-        op.kind = 1;
-        // two entries per lane and pass, at least 4 lanes per row (measured best
-        // over 1-4 entries and 1-4 lanes on the V-cycle of the 4.49M-DOF model)
         double mean = A.n > 0 ? (double)A.nnz / A.n : 1.0;
-        const int U = 2;
-        int G = 4;
-        while (G < 64 && G * U < mean) G <<= 1;
-        op.G = G;
-        op.U = U;
+        if (maxw <= CSRS_CAP / 2) {
+            op.kind = 2;
+            const int64_t chunk = CSRS_CAP - maxw;
+            op.nb = (int)std::max<int64_t>(1, (A.nnz + chunk - 1) / chunk);
+            op.L = mean < 4 ? 1 : (mean < 32 ? 4 : 8);
+            op.desc = H.get<int2>(op.nb + 1, what);
+            csrs_desc<<<ceil_div(A.n + 1, 256), 256, 0, st>>>(A.rowptr, A.n, chunk, op.nb, op.desc);
+            DP_LAUNCH_CHECK();
+        } else {
+            op.kind = 1;
+            // two entries per lane and pass, at least 4 lanes per row (measured best
+            // over 1-4 entries and 1-4 lanes on the V-cycle of the 4.49M-DOF model)
+            const int U = 2;
+            int G = 4;
+            while (G < 64 && G * U < mean) G <<= 1;
+            op.G = G;
+            op.U = U;
+        }
         op.rowptr = A.rowptr;
         op.col = A.col;
         if (s->fp32) {
@@ -1357,6 +1387,71 @@ __global__ void __launch_bounds__(256) csrv_kernel(const int* __restrict__ rowpt
     }
 }
 
+// The CSR operator in row blocks (desc from csrs_desc): every product of the
+// block's entries is formed with coalesced loads into LDS, CSRS_K per thread
+// issued together, then each row is summed by L lanes (strided partial sums in
+// entry order, combined by a fixed butterfly).
+template <class T, int MODE, int L>
+__global__ void __launch_bounds__(CSRS_NT) csrs_kernel(const int2* __restrict__ desc,
+                                                       const int* __restrict__ rowptr, const int* __restrict__ col,
+                                                       const T* __restrict__ val, const T* __restrict__ dinv,
+                                                       const T* __restrict__ b, const T* __restrict__ x, T* y,
+                                                       T* y2) {
+    __shared__ T prod[CSRS_CAP];
+    const int tid = threadIdx.x;
+    const int2 d0 = desc[blockIdx.x], d1 = desc[blockIdx.x + 1];
+    const int r0 = d0.x, r1 = d1.x, e0 = d0.y, e1 = d1.y;
+    int c[CSRS_K];
+    T v[CSRS_K];
+#pragma unroll
+    for (int u = 0; u < CSRS_K; ++u) {
+        const int e = e0 + tid + u * CSRS_NT;
+        c[u] = e < e1 ? col[e] : -1;
+        v[u] = e < e1 ? val[e] : T(0);
+    }
+    // the offsets of this thread's first row, fetched while the products load
+    const int ra = r0 + tid / L;
+    int pa = 0, pz = 0;
+    if (ra < r1) {
+        pa = rowptr[ra];
+        pz = rowptr[ra + 1];
+    }
+#pragma unroll
+    for (int u = 0; u < CSRS_K; ++u) {
+        if (c[u] >= 0) prod[tid + u * CSRS_NT] = v[u] * (MODE == SV_PRE ? dinv[c[u]] * b[c[u]] : x[c[u]]);
+    }
+    __syncthreads();
+    // all L lanes of a row take the same trip through this loop
+    for (int q = tid; q < (r1 - r0) * L; q += CSRS_NT) {
+        const int r = r0 + q / L, l = q % L;
+        int a = pa, z = pz;
+        if (q != tid) {
+            a = rowptr[r];
+            z = rowptr[r + 1];
+        }
+        T acc = 0;
+        for (int i = a - e0 + l; i < z - e0; i += L) acc += prod[i];
+#pragma unroll
+        for (int o = L / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, L);
+        if (l != 0) continue;
+        if (MODE == SV_Y) {
+            y[r] = acc;
+        } else if (MODE == SV_PRE) {
+            y[r] = dinv[r] * b[r];
+            y2[r] = b[r] - acc;
+        } else if (MODE == SV_PROL) {
+            y[r] += acc;
+        } else if (MODE == SV_YD) {
+            y[r] = acc;
+            y2[r] = dinv[r] * acc;
+        } else if (MODE == SV_RES) {
+            y[r] = b[r] - acc;
+        } else {
+            y[r] = x[r] + dinv[r] * (b[r] - acc);
+        }
+    }
+}
+
 template <class T, int MODE, int U>
 static void csrv_launch(dp_sim* s, const Op& op, const T* v, const T* dinv, const T* b, const T* x, T* y,
                         T* y2) {
@@ -1377,6 +1472,14 @@ static void op_launch(dp_sim* s, const Op& op, const T* dinv, const T* b, const 
         const Sell& S = op.s;
         sell_kernel<T, MODE><<<ceil_div(S.n, 256), 256, 0, s->stream>>>(S.sptr, S.col, (const T*)S.val, S.n,
                                                                         dinv, b, x, y, y2);
+    } else if (op.kind == 2) {
+        const T* v = (const T*)op.val;
+        switch (op.L) {
+            case 1: csrs_kernel<T, MODE, 1><<<op.nb, CSRS_NT, 0, s->stream>>>(op.desc, op.rowptr, op.col, v, dinv, b, x, y, y2); break;
+            case 4: csrs_kernel<T, MODE, 4><<<op.nb, CSRS_NT, 0, s->stream>>>(op.desc, op.rowptr, op.col, v, dinv, b, x, y, y2); break;
+            case 8: csrs_kernel<T, MODE, 8><<<op.nb, CSRS_NT, 0, s->stream>>>(op.desc, op.rowptr, op.col, v, dinv, b, x, y, y2); break;
+            default: throw Error(DP_E_INVALID, "blocked CSR operator built with another lane count");
+        }
     } else {
         const T* v = (const T*)op.val;
         if (op.U != 2) throw Error(DP_E_INVALID, "CSR operator built for another unroll");

@@ -87,13 +87,17 @@ struct Sell {
 // An operator of the V-cycle in the apply precision: SELL-64 when its rows are
 // short and even, else CSR processed by G lanes per row.
 struct Op {
-    int kind = 0;  // 0 SELL-64, 1 CSR with G lanes per row, U entries per lane and pass
-    int n = 0, G = 4, U = 1;
+    // 0 SELL-64; 1 CSR with G lanes per row, U entries per lane and pass;
+    // 2 CSR in row blocks of bounded entry count (nb blocks described by desc),
+    //   L lanes per row in the row sums
+    int kind = 0;
+    int n = 0, G = 4, U = 1, L = 4, nb = 0;
     int64_t nnz = 0;
     Sell s;
     int* rowptr = nullptr;
     int* col = nullptr;
     void* val = nullptr;
+    int2* desc = nullptr;
 };
 
 struct AmgLevel {

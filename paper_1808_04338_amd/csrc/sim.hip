@@ -839,8 +839,8 @@ double kernel_bytes(dp_sim* s, int kernel) {
             // two sweeps over A (pre: b, dinv gathered; post: x), P and R once,
             // vectors: b, x, r, t, dinv
             auto opb = [&](const Op& o) {
-                return o.kind == 0 ? o.s.nel * (4 + es) + 4.0 * (o.s.nslices + 1)
-                                   : o.nnz * (4 + es) + 4.0 * (o.n + 1);
+                if (o.kind == 0) return o.s.nel * (4 + es) + 4.0 * (o.s.nslices + 1);
+                return o.nnz * (4 + es) + 4.0 * (o.n + 1) + (o.kind == 2 ? 8.0 * (o.nb + 1) : 0.0);
             };
             b += 2.0 * opb(L.Aop) + opb(L.Pop) + opb(L.Rop);
             b += 8.0 * L.n * es;
