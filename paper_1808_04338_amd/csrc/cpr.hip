@@ -27,15 +27,19 @@ void cpr_setup(dp_sim* s) {
 // FPF: z1 = F^-1 r; FP: z1 = 0.  Then the pressure stage, z2 = z1 + R^T e,
 // t = r - A z2, z1 = F^-1 t (the caller adds z2 + z1).  Every pointer is fixed between setups, so the whole
 // sequence can be captured into a HIP graph when r is the handle's own buffer.
+// Folded form (FPF only): r is formed from sc * r64 by the first ILU sweeps and
+// the last ones write zout = z2 + z1 in FP64.
 template <class T>
-static void apply_core(dp_sim* s, const V2<T>* r) {
+static void apply_core(dp_sim* s, const V2<T>* r, const d2* r64 = nullptr, double sc = 1.0,
+                       d2* zout = nullptr) {
     V2<T>* z1 = (V2<T>*)s->pz;
     V2<T>* z2 = (V2<T>*)s->pz2;
     V2<T>* t = (V2<T>*)s->pt;
+    if (r64 && s->desc.cpr_variant == DP_CPR_FP) fail(DP_E_INVALID, "folded casts need the FPF form");
     // FP starts the pressure stage from z1 = 0 (a fill kernel, not a memset:
     // the sequence may be captured into a graph)
     if (s->desc.cpr_variant == DP_CPR_FP) vec_fill_zero<T>(s, (T*)z1, 2 * (int64_t)s->topo.nb);
-    else ilu_solve<T>(s, r, z1);
+    else ilu_solve<T>(s, r, z1, r64, sc);
     bresidual_p<T>(s, r, z1, (T*)s->levels[0].b);
     T* e;
     {
@@ -44,7 +48,7 @@ static void apply_core(dp_sim* s, const V2<T>* r) {
         ks.bytes(kernel_bytes(s, 2));
     }
     bresidual_prol<T>(s, r, z1, e, z2, t);
-    ilu_solve<T>(s, t, z1);
+    ilu_solve<T>(s, t, z1, nullptr, 1.0, zout ? z2 : nullptr, zout);
 }
 
 // Capture apply_core on the handle's stream (its input the handle's buffer pr)
@@ -106,12 +110,17 @@ void cpr_apply(dp_sim* s, const double* r, double* z, double scale) {
     const bool graph = !s->timing && (mode == 2 || (mode == 0 && len < PRECOND_GRAPH_DOF));
     // the core reads the handle's buffer pr, except unscaled eager FP64 (r itself)
     const bool own = s->fp32 || graph || scale != 1.0;
-    if (s->fp32) to_f32(s, r, (float*)s->pr, len, scale);
-    else if (scale != 1.0) vec_scale_to(s, r, scale, (double*)s->pr, len);
-    else if (graph) copy_f64(s, r, (double*)s->pr, len);
+    // eager FP32 CPR-FPF: the casts to and from FP32 run inside the ILU sweeps
+    const bool fold = s->fp32 && !graph && s->desc.cpr_variant != DP_CPR_FP;
+    if (s->fp32 && !fold) to_f32(s, r, (float*)s->pr, len, scale);
+    else if (!s->fp32 && scale != 1.0) vec_scale_to(s, r, scale, (double*)s->pr, len);
+    else if (!s->fp32 && graph) copy_f64(s, r, (double*)s->pr, len);
     if (graph) {
         if (!s->pc_graph_ok) capture_precond(s);
         DP_HIP(hipGraphLaunch(s->pc_exec, s->stream));
+    } else if (fold) {
+        apply_core<float>(s, (const f2*)s->pr, (const d2*)r, scale, (d2*)z);
+        return;
     } else if (s->fp32) {
         apply_core<float>(s, (const f2*)s->pr);
     } else {

@@ -36,7 +36,13 @@ template <class T> void bresidual_p(dp_sim* s, const V2<T>* b, const V2<T>* x, T
 template <class T>
 void bresidual_prol(dp_sim* s, const V2<T>* b, const V2<T>* x, const T* e, V2<T>* x2, V2<T>* y);
 template <class T> void ilu_factor(dp_sim* s);
-template <class T> void ilu_solve(dp_sim* s, const V2<T>* r, V2<T>* z);
+// z = (LU)^-1 r.  With r64 given, r is formed on the fly as (T)(sc * r64) and
+// written to r (then writable) on first use; with zout given, every final z
+// entry is also written as zout = (double)(zadd + z).  Both fold the precision
+// casts around the FP32 preconditioner into the sweeps.
+template <class T>
+void ilu_solve(dp_sim* s, const V2<T>* r, V2<T>* z, const d2* r64 = nullptr, double sc = 1.0,
+               const V2<T>* zadd = nullptr, d2* zout = nullptr);
 
 // krylov.hip (FP64 vectors of length len doubles)
 void vec_copy(dp_sim* s, const double* x, double* y, int64_t len);

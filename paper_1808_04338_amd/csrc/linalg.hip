@@ -571,7 +571,34 @@ struct IluSolveArgs {
     IluArgs<T> f;
     const V2<T>* r;
     V2<T>* z;
+    const d2* r64;     // optional FP64 right-hand side, scaled by sc on first read
+    double sc;
+    const V2<T>* zadd;  // optional: final entries also written as zout = zadd + z
+    d2* zout;
 };
+
+// First read of r[i]: from r64 (scaled, rounded to T and kept in r for the later
+// reads of the same solve and of the caller) or from r itself.
+template <class T>
+__device__ inline V2<T> ilus_rin(const IluSolveArgs<T>& a, int64_t i) {
+    if (a.r64) {
+        const d2 v = a.r64[i];
+        const V2<T> x = mk2<T>((T)(a.sc * v.x), (T)(a.sc * v.y));
+        const_cast<V2<T>*>(a.r)[i] = x;
+        return x;
+    }
+    return a.r[i];
+}
+
+// Final z[i]; with zout also the FP64 sum zadd + z, rounded as its FP32 sum.
+template <class T>
+__device__ inline void ilus_zfin(const IluSolveArgs<T>& a, int64_t i, V2<T> v) {
+    a.z[i] = v;
+    if (a.zout) {
+        const V2<T> u = a.zadd[i];
+        a.zout[i] = mk2<double>((double)(u.x + v.x), (double)(u.y + v.y));
+    }
+}
 
 template <class T>
 __global__ void ilus_red_fwd(IluSolveArgs<T> a) {
@@ -579,7 +606,8 @@ __global__ void ilus_red_fwd(IluSolveArgs<T> a) {
     if (q >= a.f.nred) return;
     int n = a.f.n;
     int c = q;  // the matrix node of fracture row q
-    V2<T> y = vsub(a.r[n + q], bmv(ldb(a.f.F.l0, a.f.F.l1, (int64_t)6 * n + q), a.r[c]));
+    const V2<T> rm = ilus_rin(a, c);
+    V2<T> y = vsub(ilus_rin(a, n + q), bmv(ldb(a.f.F.l0, a.f.F.l1, (int64_t)6 * n + q), rm));
     a.z[n + q] = y;
 }
 
@@ -589,8 +617,8 @@ __global__ void ilus_black(IluSolveArgs<T> a) {
     if (q >= a.f.n) return;
     int n = a.f.n;
     int c = q;  // the matrix node of fracture row q
-    V2<T> rm = a.r[c];
-    V2<T> y = vsub(a.r[n + q], bmv(ldb(a.f.F.l0, a.f.F.l1, (int64_t)6 * n + q), rm));
+    V2<T> rm = ilus_rin(a, c);
+    V2<T> y = vsub(ilus_rin(a, n + q), bmv(ldb(a.f.F.l0, a.f.F.l1, (int64_t)6 * n + q), rm));
     unsigned mask = a.f.fmask[q];
 #pragma unroll
     for (int s = 0; s < 6; ++s)
@@ -601,8 +629,8 @@ __global__ void ilus_black(IluSolveArgs<T> a) {
         return;
     }
     V2<T> zb = bmv(ldb(a.f.F.ui0, a.f.F.ui1, n + q), y);
-    a.z[n + q] = zb;
-    a.z[c] = bmv(ldb(a.f.F.ui0, a.f.F.ui1, c), vsub(rm, bmv(ldb(a.f.A.m0, a.f.A.m1, c), zb)));
+    ilus_zfin(a, n + q, zb);
+    ilus_zfin(a, c, bmv(ldb(a.f.F.ui0, a.f.F.ui1, c), vsub(rm, bmv(ldb(a.f.A.m0, a.f.A.m1, c), zb))));
 }
 
 template <class T>
@@ -631,9 +659,9 @@ __global__ void ilus_well(IluSolveArgs<T> a) {
             s0 += sh0[i];
             s1 += sh1[i];
         }
-        V2<T> rw = a.r[2 * n + w];
+        V2<T> rw = ilus_rin(a, 2 * n + w);
         V2<T> zw = bmv(ldb(a.f.F.ui0, a.f.F.ui1, 2 * n + w), mk2<T>(rw.x - s0, rw.y - s1));
-        a.z[2 * n + w] = zw;
+        ilus_zfin(a, 2 * n + w, zw);
         zw_sh = zw;
     }
     __syncthreads();
@@ -644,8 +672,9 @@ __global__ void ilus_well(IluSolveArgs<T> a) {
         int c = q;  // the matrix node of fracture row q
         V2<T> y = vsub(a.z[n + q], bmv(ldb(a.f.F.ubw0, a.f.F.ubw1, p), zw));
         V2<T> zb = bmv(ldb(a.f.F.ui0, a.f.F.ui1, n + q), y);
-        a.z[n + q] = zb;
-        a.z[c] = bmv(ldb(a.f.F.ui0, a.f.F.ui1, c), vsub(a.r[c], bmv(ldb(a.f.A.m0, a.f.A.m1, c), zb)));
+        ilus_zfin(a, n + q, zb);
+        // r[c] of a black row was formed by the black sweep
+        ilus_zfin(a, c, bmv(ldb(a.f.F.ui0, a.f.F.ui1, c), vsub(a.r[c], bmv(ldb(a.f.A.m0, a.f.A.m1, c), zb))));
     }
 }
 
@@ -664,24 +693,29 @@ __global__ void ilus_red_bwd(IluSolveArgs<T> a) {
     int p = a.f.fperf[q];
     if (p >= 0) y = vsub(y, bmv(ldb(a.f.F.ubw0, a.f.F.ubw1, p), a.z[2 * n + a.f.perf_well[p]]));
     V2<T> zr = bmv(ldb(a.f.F.ui0, a.f.F.ui1, n + q), y);
-    a.z[n + q] = zr;
-    a.z[c] = bmv(ldb(a.f.F.ui0, a.f.F.ui1, c), vsub(a.r[c], bmv(ldb(a.f.A.m0, a.f.A.m1, c), zr)));
+    ilus_zfin(a, n + q, zr);
+    // r[c] of a red row was formed by the forward sweep
+    ilus_zfin(a, c, bmv(ldb(a.f.F.ui0, a.f.F.ui1, c), vsub(a.r[c], bmv(ldb(a.f.A.m0, a.f.A.m1, c), zr))));
 }
 
 template <class T>
-void ilu_solve(dp_sim* s, const V2<T>* r, V2<T>* z) {
+void ilu_solve(dp_sim* s, const V2<T>* r, V2<T>* z, const d2* r64, double sc, const V2<T>* zadd, d2* zout) {
     Topo& t = s->topo;
-    IluSolveArgs<T> a{ilu_args<T>(s), r, z};
+    if (zout && !zadd) fail(DP_E_INVALID, "ILU solve: the sum output needs its addend");
+    IluSolveArgs<T> a{ilu_args<T>(s), r, z, r64, sc, zadd, zout};
     int nb_red = ceil_div(t.nred, 256), nb_black = ceil_div(t.n - t.nred, 256);
     KtScope ks(s->capturing ? nullptr : &s->kt[1], s->stream);
-    ks.bytes(kernel_bytes(s, 1));
+    // the folded casts: r64 read and r written in place of the r read; zadd read
+    // and zout written
+    const double es = sizeof(T), nb = t.nb;
+    ks.bytes(kernel_bytes(s, 1) + (r64 ? 16.0 * nb : 0.0) + (zout ? nb * (2 * es + 16.0) : 0.0));
     if (nb_red) ilus_red_fwd<T><<<nb_red, 256, 0, s->stream>>>(a);
     if (nb_black) ilus_black<T><<<nb_black, 256, 0, s->stream>>>(a);
     if (t.nw) ilus_well<T><<<t.nw, 256, 0, s->stream>>>(a);
     if (nb_red) ilus_red_bwd<T><<<nb_red, 256, 0, s->stream>>>(a);
     DP_LAUNCH_CHECK();
 }
-template void ilu_solve<double>(dp_sim*, const d2*, d2*);
-template void ilu_solve<float>(dp_sim*, const f2*, f2*);
+template void ilu_solve<double>(dp_sim*, const d2*, d2*, const d2*, double, const d2*, d2*);
+template void ilu_solve<float>(dp_sim*, const f2*, f2*, const d2*, double, const f2*, d2*);
 
 }  // namespace dp
