@@ -151,6 +151,11 @@ typedef struct {
                                  have not lowered the smallest CNV of its updated iterates
                                  (iterations 1, 2, ...; iteration 0 is the start state); 0 or
                                  less leaves max_newton as the only limit [off] */
+    int32_t fail_setup;       /* test hook for the error paths: when > 0, the fail_setup-th AMG
+                                 setup of the handle (counted from 1 over its lifetime) fails
+                                 with DP_E_NOMEM right after its first level's launches are
+                                 queued, as a workspace overflow in the middle of a setup
+                                 would; 0 or less never [off] */
 } dp_sim_desc;
 
 typedef struct {

@@ -58,7 +58,7 @@ class DpSimDesc(C.Structure):
                 ("forcing_beta", C.c_double), ("forcing_eta_min", C.c_double),
                 ("forcing_eta_max", C.c_double), ("precond_eager", C.c_int32),
                 ("decoupling", C.c_int32), ("cpr_variant", C.c_int32),
-                ("newton_stall", C.c_int32)]
+                ("newton_stall", C.c_int32), ("fail_setup", C.c_int32)]
 
 
 class DpNewtonInfo(C.Structure):

@@ -909,35 +909,42 @@ __global__ void csrs_desc(const int* __restrict__ rowptr, int n, int64_t chunk, 
     for (int64_t k = lo / chunk + 1; k * chunk <= hi && k < nb; ++k) desc[k] = make_int2(r, (int)hi);
 }
 
+// The slice widths of SELL-64 (their scan in w) and the longest row of A, read
+// back into two pinned slots with the caller's one synchronisation.
+struct OpShape {
+    int nsl = 0;
+    int64_t* w = nullptr;
+    int64_t total = 0, maxw = 0;
+};
+
+static void op_measure(dp_sim* s, const Csr& A, OpShape& m, Arena& Sc, int64_t* hslots) {
+    hipStream_t st = s->stream;
+    m.nsl = (A.n + 63) / 64;
+    m.w = Sc.get<int64_t>(m.nsl + 2, "sell widths");
+    int64_t* tmp = Sc.get<int64_t>(scan_tmp_size(m.nsl + 2), "sell scan");
+    int* dmax = Sc.get<int>(1, "sell width");
+    if (m.nsl == 0) return;
+    DP_HIP(hipMemsetAsync(dmax, 0, sizeof(int), st));
+    sell_width<<<ceil_div(m.nsl + 1, 256), 256, 0, st>>>(A, m.nsl, m.w, dmax);
+    DP_LAUNCH_CHECK();
+    scan_inplace(st, m.w, m.nsl + 1, tmp);
+    DP_HIP(hipMemcpyAsync(&hslots[0], m.w + m.nsl, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    DP_HIP(hipMemcpyAsync(&hslots[1], dmax, sizeof(int), hipMemcpyDeviceToHost, st));
+}
+
 // Choose and build the apply form of a CSR operator.  SELL-64 when it pads by
 // at most 30% and no row is longer than 48; otherwise row blocks of at most
 // CSRS_CAP entries when no row is longer than half of that, with 4 lanes per
 // row in the sums (8 from a mean of 32 entries per row); otherwise CSR with G
 // lanes per row (G the power of two at or above the mean row length, 4..64).
-static void build_op(dp_sim* s, const Csr& A, Op& op, bool pad_self, Arena& H, Arena& Sc,
+static void op_build(dp_sim* s, const Csr& A, Op& op, bool pad_self, const OpShape& m, Arena& H,
                      const char* what) {
     hipStream_t st = s->stream;
     op.n = A.n;
     op.nnz = A.nnz;
-    int nsl = (A.n + 63) / 64;
-    size_t mark = Sc.top;
-    int64_t* w = Sc.get<int64_t>(nsl + 2, "sell widths");
-    int64_t* tmp = Sc.get<int64_t>(scan_tmp_size(nsl + 2), "sell scan");
-    int* dmax = Sc.get<int>(1, "sell width");
-    int64_t total = 0;
-    int64_t maxw = 0;
-    if (nsl > 0) {
-        DP_HIP(hipMemsetAsync(dmax, 0, sizeof(int), st));
-        sell_width<<<ceil_div(nsl + 1, 256), 256, 0, st>>>(A, nsl, w, dmax);
-        DP_LAUNCH_CHECK();
-        scan_inplace(st, w, nsl + 1, tmp);
-        int64_t* h = pinned_slots() + 1;
-        DP_HIP(hipMemcpyAsync(&h[0], w + nsl, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-        DP_HIP(hipMemcpyAsync(&h[1], dmax, sizeof(int), hipMemcpyDeviceToHost, st));
-        DP_HIP(hipStreamSynchronize(st));
-        total = h[0];
-        maxw = *reinterpret_cast<int*>(&h[1]);
-    }
+    const int nsl = m.nsl;
+    int64_t* w = m.w;
+    const int64_t total = m.total, maxw = m.maxw;
     bool sell = total <= (int64_t)(1.3 * (double)A.nnz) + 64 && maxw <= 48;
     size_t es = s->fp32 ? sizeof(float) : sizeof(double);
     if (sell) {
@@ -987,6 +994,30 @@ static void build_op(dp_sim* s, const Csr& A, Op& op, bool pad_self, Arena& H, A
             op.val = A.val;
         }
     }
+}
+
+// The apply forms of a level's A, P and R, with one host synchronisation for
+// the three shapes.
+static void build_level_ops(dp_sim* s, const Csr& A, const Csr& P, const Csr& R, AmgLevel& L, Arena& H,
+                            Arena& Sc) {
+    const size_t mark = Sc.top;
+    int64_t* h = pinned_slots() + 1;  // slots 1..6: (total, longest row) of A, P, R
+    const Csr* src[3] = {&A, &P, &R};
+    OpShape m[3];
+    bool any = false;
+    for (int k = 0; k < 3; ++k) {
+        op_measure(s, *src[k], m[k], Sc, h + 2 * k);
+        any = any || m[k].nsl > 0;
+    }
+    if (any) DP_HIP(hipStreamSynchronize(s->stream));
+    for (int k = 0; k < 3; ++k) {
+        if (m[k].nsl == 0) continue;
+        m[k].total = h[2 * k];
+        m[k].maxw = *reinterpret_cast<const int*>(&h[2 * k + 1]);
+    }
+    op_build(s, A, L.Aop, true, m[0], H, "A apply");
+    op_build(s, P, L.Pop, false, m[1], H, "P apply");
+    op_build(s, R, L.Rop, false, m[2], H, "R apply");
     Sc.top = mark;
 }
 
@@ -1043,12 +1074,16 @@ void amg_setup(dp_sim* s) {
     s->coarse_inv = nullptr;
     s->coarse_n = 0;
     const dp_sim_desc& d = s->desc;
+    ++s->amg_setups;
     Csr A = s->Ap0;
     for (;;) {
         AmgLevel L;
         L.n = A.n;
         L.A = A;
         level_apply_data(s, L, H, Sc);
+        // error-path test hook: the first level's launches are queued
+        if (s->levels.empty() && d.fail_setup > 0 && s->amg_setups == d.fail_setup)
+            fail(DP_E_NOMEM, "AMG setup " + std::to_string(s->amg_setups) + " failed (fail_setup test hook)");
         bool last = (A.n <= d.amg_coarse_max) || ((int)s->levels.size() + 1 >= d.amg_max_levels);
         int n = A.n;
         int nc = 0;
@@ -1260,9 +1295,7 @@ void amg_setup(dp_sim* s) {
         Sc.top = smark;
         L.nc = nc;
         L.R = R;
-        build_op(s, A, L.Aop, true, H, Sc, "A apply");
-        build_op(s, L.P, L.Pop, false, H, Sc, "P apply");
-        build_op(s, R, L.Rop, false, H, Sc, "R apply");
+        build_level_ops(s, A, L.P, R, L, H, Sc);
         s->levels.push_back(L);
         A = Ac;
     }

@@ -220,6 +220,7 @@ struct dp_sim {
     unsigned int* red_count = nullptr;
     int red_blocks = 0;
     int64_t seg_fallbacks = 0;  // AMG products that took the global sort path
+    int64_t amg_setups = 0;     // AMG setups begun over the handle's lifetime
 
     // sort / setup scratch (part of the per-setup region)
     size_t scratch_bytes = 0;

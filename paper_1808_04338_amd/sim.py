@@ -84,6 +84,7 @@ def make_desc(model, precision=None, **opts):
     d.decoupling = {"gj": 0, "abf": 1, "ti": 2}[opts.get("decoupling", "gj")]
     d.cpr_variant = {"fpf": 0, "fp": 1}[opts.get("cpr_variant", "fpf")]
     d.newton_stall = int(opts.get("newton_stall", 0))
+    d.fail_setup = int(opts.get("fail_setup", 0))
     return d, keep
 
 

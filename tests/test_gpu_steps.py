@@ -135,6 +135,38 @@ def test_failed_step_rolls_back_and_leaves_the_handle_usable():
     b.close()
 
 
+def test_setup_failure_rolls_back_and_leaves_the_handle_usable():
+    """A workspace error in the middle of an AMG setup (the fail_setup hook:
+    the handle's second setup fails with DP_E_NOMEM once its first level's
+    launches are queued, i.e. in the second Newton iteration of the step)
+    ends the timestep with DP_E_NOMEM and the state of the start of the step,
+    bitwise; the same handle then takes the step to the same bits as a fresh
+    handle, so controls and work buffers were left usable too.  Forced from
+    the host: no kernel fails."""
+    from paper_1808_04338_amd import Sim
+    from paper_1808_04338_amd._lib import DP_E_NOMEM, DpError
+
+    m = synth.served_realisation(0, (20, 20, 10))
+    opts = dict(newton_tol=1e-10, lin_rtol=1e-12)
+    a = Sim(m, fail_setup=2, **opts)
+    before = a.get_state()
+    dt = m["schedule"][0]
+    with pytest.raises(DpError) as e:
+        a.timestep(dt)
+    assert e.value.code == DP_E_NOMEM
+    assert "fail_setup" in str(e.value)
+    for u, v in zip(before, a.get_state()):
+        assert np.array_equal(u, v)
+    info_a = a.timestep(dt)
+    b = Sim(m, **opts)
+    info_b = b.timestep(dt)
+    assert info_a["newton_iters"] == info_b["newton_iters"] >= 2
+    for u, v in zip(a.get_state(), b.get_state()):
+        assert np.array_equal(u, v)
+    a.close()
+    b.close()
+
+
 def test_layered_five_spot_schedule_matches_oracle():
     """The 144k-DOF configuration's physics, layered permeability and five-spot
     (four injectors, one producer) with its 5-day steps, at the smallest size
