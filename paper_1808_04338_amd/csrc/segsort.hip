@@ -78,12 +78,46 @@ struct ProdSrc {
     double* oval;
 };
 
-// The bitonic network over KPL * WAVE keys of one wavefront, in registers:
-// element e = KPL * lane + i sits in register i of its lane.  Stages with a
-// distance j below KPL compare registers of one lane; the others exchange the
-// same register with lane ^ (j / KPL).  Element e keeps the minimum of its pair
-// when (e is the lower of the pair) == (the pair sorts ascending, e & k == 0),
-// exactly the compare-exchange of the LDS network.
+// Bitonic stages in registers over a wavefront's KPL * WAVE consecutive keys
+// starting at element base: element e = base + KPL * lane + i sits in register
+// i of its lane.  Stages j = jstart, jstart / 2, ..., 1 of merge step k: those
+// with a distance below KPL compare registers of one lane, the others exchange
+// the same register with lane ^ (j / KPL).  Element e keeps the minimum of its
+// pair when (e is the lower of the pair) == (the pair sorts ascending,
+// e & k == 0), exactly the compare-exchange of the LDS network.
+template <int KPL>
+__device__ inline void reg_stages(uint64_t (&v)[KPL], int base, int k, int jstart) {
+    const int lane = threadIdx.x % WAVE;
+    const int e0 = base + KPL * lane;
+#pragma unroll
+    for (int j = jstart; j > 0; j >>= 1) {
+        if (j < KPL) {
+#pragma unroll
+            for (int i = 0; i < KPL; ++i) {
+                if ((i & j) == 0) {
+                    const int l = i | j;
+                    const bool up = ((e0 + i) & k) == 0;
+                    const uint64_t a = v[i], b = v[l];
+                    const uint64_t mn = a < b ? a : b, mx = a < b ? b : a;
+                    v[i] = up ? mn : mx;
+                    v[l] = up ? mx : mn;
+                }
+            }
+        } else {
+            const int lj = j / KPL;
+            const bool lower = (lane & lj) == 0;
+#pragma unroll
+            for (int i = 0; i < KPL; ++i) {
+                const uint64_t o = __shfl_xor(v[i], lj, WAVE);
+                const bool up = ((e0 + i) & k) == 0;
+                const uint64_t mn = v[i] < o ? v[i] : o, mx = v[i] < o ? o : v[i];
+                v[i] = (lower == up) ? mn : mx;
+            }
+        }
+    }
+}
+
+// The whole bitonic network over the KPL * WAVE keys of one wavefront.
 template <int KPL>
 __device__ inline void wave_bitonic(uint64_t* key) {
     const int lane = threadIdx.x % WAVE;
@@ -92,36 +126,51 @@ __device__ inline void wave_bitonic(uint64_t* key) {
 #pragma unroll
     for (int i = 0; i < KPL; ++i) v[i] = key[KPL * lane + i];
 #pragma unroll
-    for (int k = 2; k <= N; k <<= 1) {
-#pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
-            if (j < KPL) {
-#pragma unroll
-                for (int i = 0; i < KPL; ++i) {
-                    if ((i & j) == 0) {
-                        const int l = i | j;
-                        const bool up = ((KPL * lane + i) & k) == 0;
-                        const uint64_t a = v[i], b = v[l];
-                        const uint64_t mn = a < b ? a : b, mx = a < b ? b : a;
-                        v[i] = up ? mn : mx;
-                        v[l] = up ? mx : mn;
-                    }
-                }
-            } else {
-                const int lj = j / KPL;
-                const bool lower = (lane & lj) == 0;
-#pragma unroll
-                for (int i = 0; i < KPL; ++i) {
-                    const uint64_t o = __shfl_xor(v[i], lj, WAVE);
-                    const bool up = ((KPL * lane + i) & k) == 0;
-                    const uint64_t mn = v[i] < o ? v[i] : o, mx = v[i] < o ? o : v[i];
-                    v[i] = (lower == up) ? mn : mx;
-                }
-            }
-        }
-    }
+    for (int k = 2; k <= N; k <<= 1) reg_stages<KPL>(v, 0, k, k >> 1);
 #pragma unroll
     for (int i = 0; i < KPL; ++i) key[KPL * lane + i] = v[i];
+}
+
+// The bitonic network over P2 = 4 KPL WAVE keys of a 256-thread workgroup:
+// every wavefront sorts its quarter in registers (the merge steps up to the
+// quarter's size), and each larger merge step k takes its stages of distance
+// at least a quarter in LDS, the rest in registers.  Every stage compares the
+// same pairs in the same direction as the plain LDS network.
+template <int KPL>
+__device__ __forceinline__ void block_bitonic(uint64_t* key) {
+    constexpr int C = KPL * WAVE, P2 = 4 * C, NT = 4 * WAVE;
+    const int tid = threadIdx.x, lane = tid % WAVE;
+    const int base = (tid / WAVE) * C;
+    uint64_t v[KPL];
+#pragma unroll
+    for (int i = 0; i < KPL; ++i) v[i] = key[base + KPL * lane + i];
+#pragma unroll
+    for (int k = 2; k <= C; k <<= 1) reg_stages<KPL>(v, base, k, k >> 1);
+#pragma unroll
+    for (int i = 0; i < KPL; ++i) key[base + KPL * lane + i] = v[i];
+#pragma unroll
+    for (int k = 2 * C; k <= P2; k <<= 1) {
+        __syncthreads();
+        for (int j = k >> 1; j >= C; j >>= 1) {
+            for (int p = tid; p < (P2 >> 1); p += NT) {
+                const int i = ((p & ~(j - 1)) << 1) | (p & (j - 1));
+                const int l = i + j;
+                const bool up = (i & k) == 0;
+                const uint64_t a = key[i], b = key[l];
+                if ((a > b) == up) {
+                    key[i] = b;
+                    key[l] = a;
+                }
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int i = 0; i < KPL; ++i) v[i] = key[base + KPL * lane + i];
+        reg_stages<KPL>(v, base, k, C >> 1);
+#pragma unroll
+        for (int i = 0; i < KPL; ++i) key[base + KPL * lane + i] = v[i];
+    }
+    __syncthreads();
 }
 
 template <int NT, int MAXE, class Src>
@@ -200,6 +249,14 @@ __device__ void tile_run(SegTile<MAXE>& T, const Src& S, int ra, int rb, int64_t
         if (P2 <= 2 * WAVE) wave_bitonic<2>(T.key);
         else wave_bitonic<4>(T.key);
         __syncthreads();
+    } else if constexpr (NT == 4 * WAVE && MAXE >= 4 * WAVE * 2) {
+        // P2 >= 2 NT = 512 here
+        if (P2 == 512) block_bitonic<2>(T.key);
+        else if (P2 == 1024) block_bitonic<4>(T.key);
+        else if constexpr (MAXE >= 2048) {
+            if (P2 == 2048) block_bitonic<8>(T.key);
+            else if constexpr (MAXE >= 4096) block_bitonic<16>(T.key);
+        }
     } else {
         for (int k = 2; k <= P2; k <<= 1) {
             for (int j = k >> 1; j > 0; j >>= 1) {
