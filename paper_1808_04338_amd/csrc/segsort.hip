@@ -42,6 +42,8 @@ struct SegTile {
     unsigned char erow[MAXE];  // product mode: tile-local row of every X entry
     int64_t rowoff[SEG_GMAX + 1];  // term offsets of the tile's rows
     int xoff[SEG_GMAX + 1];        // product mode: X entry offsets of the tile's rows
+    int nh;                        // workgroup tiles: heads listed (in eo)
+    int wsum[4];                   // workgroup tiles: kept heads per wavefront quarter
 };
 
 __device__ inline int pow2ceil(int x) {
@@ -275,20 +277,67 @@ __device__ void tile_run(SegTile<MAXE>& T, const Src& S, int ra, int rb, int64_t
         }
     }
     // run sums at the heads, in term order within each run; a head's sum goes to
-    // its own term's slot (every run reads only its own terms)
-    for (int t = tid; t < total; t += NT) {
-        uint64_t rc = T.key[t] >> IB;
-        bool head = t == 0 || (T.key[t - 1] >> IB) != rc;
-        double s = 0.0;
-        if (head) {
-            for (int u = t; u < total && (T.key[u] >> IB) == rc; ++u) s += T.v[T.key[u] & IMASK];
+    // its own term's slot (every run reads only its own terms).  rank[t] is then
+    // 1 at a kept head (a non-zero sum), 0 elsewhere.
+    if constexpr (NT > WAVE) {
+        // long tiles: the heads are listed first (in any order, each run is summed
+        // alone) and each thread sums one run, so that a wavefront waits for one
+        // run instead of one per position it visits
+        if (tid == 0) T.nh = 0;
+        __syncthreads();
+        for (int t = tid; t < total; t += NT) {
+            const uint64_t rc = T.key[t] >> IB;
+            T.rank[t] = 0;
+            if (t == 0 || (T.key[t - 1] >> IB) != rc) T.eo[atomicAdd(&T.nh, 1)] = t;
         }
-        T.rank[t] = (head && s != 0.0) ? 1 : 0;
-        if (head) T.v[T.key[t] & IMASK] = s;
+        __syncthreads();
+        const int nh = T.nh;
+        for (int h = tid; h < nh; h += NT) {
+            const int t = T.eo[h];
+            const uint64_t rc = T.key[t] >> IB;
+            double s = 0.0;
+            for (int u = t; u < total && (T.key[u] >> IB) == rc; ++u) s += T.v[T.key[u] & IMASK];
+            T.rank[t] = s != 0.0 ? 1 : 0;
+            T.v[T.key[t] & IMASK] = s;
+        }
+    } else {
+        for (int t = tid; t < total; t += NT) {
+            uint64_t rc = T.key[t] >> IB;
+            bool head = t == 0 || (T.key[t - 1] >> IB) != rc;
+            double s = 0.0;
+            if (head) {
+                for (int u = t; u < total && (T.key[u] >> IB) == rc; ++u) s += T.v[T.key[u] & IMASK];
+            }
+            T.rank[t] = (head && s != 0.0) ? 1 : 0;
+            if (head) T.v[T.key[t] & IMASK] = s;
+        }
     }
     __syncthreads();
-    // exclusive ranks of the kept heads (wave 0, 64 at a time)
-    if (tid < WAVE) {
+    // exclusive ranks of the kept heads, 64 at a time: one wavefront over the
+    // tile, or in a workgroup tile each wavefront over a quarter, then the
+    // quarters' offsets added
+    if constexpr (NT > WAVE) {
+        static_assert(NT == 4 * WAVE, "workgroup tiles have four wavefronts");
+        const int w = tid / WAVE, lane = tid % WAVE;
+        const int q = ((total + NT - 1) / NT) * WAVE;
+        const int c_begin = w * q, c_end = min(total, c_begin + q);
+        const uint64_t lt = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+        int run = 0;
+        for (int c0 = c_begin; c0 < c_end; c0 += WAVE) {
+            const int t = c0 + lane;
+            const bool keep = t < c_end && T.rank[t] != 0;
+            const uint64_t m = __ballot(keep);
+            if (t < c_end) T.rank[t] = run + __popcll(m & lt);
+            run += __popcll(m);
+        }
+        if (lane == 0) T.wsum[w] = run;
+        __syncthreads();
+        int off = 0;
+        for (int i = 0; i < w; ++i) off += T.wsum[i];
+        if (off)
+            for (int t = c_begin + lane; t < c_end; t += WAVE) T.rank[t] += off;
+        if (tid == 0) T.rank[total] = T.wsum[0] + T.wsum[1] + T.wsum[2] + T.wsum[3];
+    } else if (tid < WAVE) {
         int run = 0;
         uint64_t lt = tid == 0 ? 0ull : (~0ull >> (64 - tid));
         for (int c0 = 0; c0 < total; c0 += WAVE) {
