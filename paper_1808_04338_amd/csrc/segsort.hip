@@ -9,7 +9,7 @@
 //     together) are sorted at once on the key (row, col, term index) -- rows
 //     stay inside their own index ranges, so groups need no merge;
 //   * a row that does not fit its group is handled alone by the wavefront when
-//     it has at most SW_MAX terms, else listed for 256-thread workgroups that
+//     it has at most SW_MAX terms, else listed for workgroup tiles that
 //     take up to SM_MAX terms (25 KB of LDS), then up to SB_MAX (101 KB);
 //   * a longer row is listed once more, and the listed rows' terms are sorted
 //     together by the stable global radix sort on (list index, column): the
@@ -28,6 +28,8 @@ namespace dp {
 constexpr int SW_MAX = 256;
 constexpr int SM_MAX = 1024;  // 25 KB of LDS per workgroup
 constexpr int SB_MAX = 4096;  // 101 KB of LDS per workgroup
+constexpr int SM_NT = 256;    // threads of a workgroup tile of SM_MAX terms
+constexpr int SB_NT = 1024;   // threads of a workgroup tile of SB_MAX terms
 constexpr int SEG_TARGET = 128;  // terms per wavefront group
 constexpr int SEG_GMAX = 64;     // rows per group
 
@@ -43,7 +45,7 @@ struct SegTile {
     int64_t rowoff[SEG_GMAX + 1];  // term offsets of the tile's rows
     int xoff[SEG_GMAX + 1];        // product mode: X entry offsets of the tile's rows
     int nh;                        // workgroup tiles: heads listed (in eo)
-    int wsum[4];                   // workgroup tiles: kept heads per wavefront quarter
+    int wsum[16];                  // workgroup tiles: kept heads per wavefront's part
 };
 
 __device__ inline int pow2ceil(int x) {
@@ -133,14 +135,14 @@ __device__ inline void wave_bitonic(uint64_t* key) {
     for (int i = 0; i < KPL; ++i) key[KPL * lane + i] = v[i];
 }
 
-// The bitonic network over P2 = 4 KPL WAVE keys of a 256-thread workgroup:
-// every wavefront sorts its quarter in registers (the merge steps up to the
-// quarter's size), and each larger merge step k takes its stages of distance
-// at least a quarter in LDS, the rest in registers.  Every stage compares the
-// same pairs in the same direction as the plain LDS network.
-template <int KPL>
+// The bitonic network over P2 = NW KPL WAVE keys of a workgroup of NW
+// wavefronts: every wavefront sorts its part in registers (the merge steps up
+// to the part's size), and each larger merge step k takes its stages of
+// distance at least a part in LDS, the rest in registers.  Every stage compares
+// the same pairs in the same direction as the plain LDS network.
+template <int KPL, int NW>
 __device__ __forceinline__ void block_bitonic(uint64_t* key) {
-    constexpr int C = KPL * WAVE, P2 = 4 * C, NT = 4 * WAVE;
+    constexpr int C = KPL * WAVE, P2 = NW * C, NT = NW * WAVE;
     const int tid = threadIdx.x, lane = tid % WAVE;
     const int base = (tid / WAVE) * C;
     uint64_t v[KPL];
@@ -251,13 +253,16 @@ __device__ void tile_run(SegTile<MAXE>& T, const Src& S, int ra, int rb, int64_t
         if (P2 <= 2 * WAVE) wave_bitonic<2>(T.key);
         else wave_bitonic<4>(T.key);
         __syncthreads();
-    } else if constexpr (NT == 4 * WAVE && MAXE >= 4 * WAVE * 2) {
-        // P2 >= 2 NT = 512 here
-        if (P2 == 512) block_bitonic<2>(T.key);
-        else if (P2 == 1024) block_bitonic<4>(T.key);
-        else if constexpr (MAXE >= 2048) {
-            if (P2 == 2048) block_bitonic<8>(T.key);
-            else if constexpr (MAXE >= 4096) block_bitonic<16>(T.key);
+    } else if constexpr (NT > WAVE && MAXE >= 2 * NT) {
+        // P2 = 2, 4, 8 or 16 times NT here (P2 >= 2 NT); KPL = P2 / NT keys per lane
+        constexpr int NW = NT / WAVE;
+        if (P2 == 2 * NT) block_bitonic<2, NW>(T.key);
+        else if constexpr (MAXE >= 4 * NT) {
+            if (P2 == 4 * NT) block_bitonic<4, NW>(T.key);
+            else if constexpr (MAXE >= 8 * NT) {
+                if (P2 == 8 * NT) block_bitonic<8, NW>(T.key);
+                else if constexpr (MAXE >= 16 * NT) block_bitonic<16, NW>(T.key);
+            }
         }
     } else {
         for (int k = 2; k <= P2; k <<= 1) {
@@ -314,10 +319,11 @@ __device__ void tile_run(SegTile<MAXE>& T, const Src& S, int ra, int rb, int64_t
     }
     __syncthreads();
     // exclusive ranks of the kept heads, 64 at a time: one wavefront over the
-    // tile, or in a workgroup tile each wavefront over a quarter, then the
-    // quarters' offsets added
+    // tile, or in a workgroup tile each wavefront over its part, then the
+    // parts' offsets added
     if constexpr (NT > WAVE) {
-        static_assert(NT == 4 * WAVE, "workgroup tiles have four wavefronts");
+        constexpr int NW = NT / WAVE;
+        static_assert(NW <= 16, "at most 16 wavefronts per workgroup tile");
         const int w = tid / WAVE, lane = tid % WAVE;
         const int q = ((total + NT - 1) / NT) * WAVE;
         const int c_begin = w * q, c_end = min(total, c_begin + q);
@@ -336,7 +342,11 @@ __device__ void tile_run(SegTile<MAXE>& T, const Src& S, int ra, int rb, int64_t
         for (int i = 0; i < w; ++i) off += T.wsum[i];
         if (off)
             for (int t = c_begin + lane; t < c_end; t += WAVE) T.rank[t] += off;
-        if (tid == 0) T.rank[total] = T.wsum[0] + T.wsum[1] + T.wsum[2] + T.wsum[3];
+        if (tid == 0) {
+            int kept = 0;
+            for (int i = 0; i < NW; ++i) kept += T.wsum[i];
+            T.rank[total] = kept;
+        }
     } else if (tid < WAVE) {
         int run = 0;
         uint64_t lt = tid == 0 ? 0ull : (~0ull >> (64 - tid));
@@ -407,8 +417,8 @@ __global__ void __launch_bounds__(WAVE) seg_wave(Src S, int nrows, int G, int64_
 // Persistent workgroups over a list of long rows (count in *nlist): rows of at
 // most MAXE terms are done here, longer ones go to the next list, or raise the
 // overflow flag when there is none.
-template <int MAXE, class Src>
-__global__ void __launch_bounds__(256) seg_block(Src S, const int* __restrict__ list, const int* nlist,
+template <int MAXE, int NT, class Src>
+__global__ void __launch_bounds__(NT) seg_block(Src S, const int* __restrict__ list, const int* nlist,
                                                  int64_t* cnt, int* next, int* nnext, int* overflow) {
     extern __shared__ char smem[];
     SegTile<MAXE>& T = *reinterpret_cast<SegTile<MAXE>*>(smem);
@@ -416,7 +426,7 @@ __global__ void __launch_bounds__(256) seg_block(Src S, const int* __restrict__ 
     for (int q = blockIdx.x; q < nl; q += gridDim.x) {
         int r = list[q];
         if (fits<MAXE>(S, r, r + 1)) {
-            tile_run<256, MAXE>(T, S, r, r + 1, cnt);
+            tile_run<NT, MAXE>(T, S, r, r + 1, cnt);
         } else if (threadIdx.x == 0) {
             cnt[r] = 0;  // set by the tier (or the global sort) that takes the row
             if (next) next[atomicAdd(nnext, 1)] = r;
@@ -654,7 +664,7 @@ static bool seg_run(hipStream_t st, const Src& S, const int64_t* off, int nrows,
     int hf[4] = {0, 0, 0, 0};
     if (nrows > 0) {
         size_t shm_m = sizeof(SegTile<SM_MAX>), shm_b = sizeof(SegTile<SB_MAX>);
-        DP_HIP(hipFuncSetAttribute((const void*)seg_block<SB_MAX, Src>,
+        DP_HIP(hipFuncSetAttribute((const void*)seg_block<SB_MAX, SB_NT, Src>,
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm_b));
         int kidx;
         {
@@ -662,9 +672,11 @@ static bool seg_run(hipStream_t st, const Src& S, const int64_t* off, int nrows,
             KtScope ks(kt, st);
             kidx = ks.idx;
             seg_wave<Src><<<ngroups, WAVE, 0, st>>>(S, nrows, G, cnt, longlist, flags);
-            seg_block<SM_MAX, Src><<<1024, 256, shm_m, st>>>(S, longlist, flags, cnt, list2, flags + 1, flags + 2);
+            seg_block<SM_MAX, SM_NT, Src><<<1024, SM_NT, shm_m, st>>>(S, longlist, flags, cnt, list2, flags + 1,
+                                                                    flags + 2);
             // rows beyond SB_MAX go back to the first list (consumed by then)
-            seg_block<SB_MAX, Src><<<256, 256, shm_b, st>>>(S, list2, flags + 1, cnt, longlist, flags + 2, flags + 3);
+            seg_block<SB_MAX, SB_NT, Src><<<256, SB_NT, shm_b, st>>>(S, list2, flags + 1, cnt, longlist, flags + 2,
+                                                                    flags + 3);
             DP_LAUNCH_CHECK();
         }
         // the flags arrive with the scan's synchronisation
