@@ -44,7 +44,7 @@ struct SegTile {
     unsigned char erow[MAXE];  // product mode: tile-local row of every X entry
     int64_t rowoff[SEG_GMAX + 1];  // term offsets of the tile's rows
     int xoff[SEG_GMAX + 1];        // product mode: X entry offsets of the tile's rows
-    int nh;                        // workgroup tiles: heads listed (in eo)
+    int nh;                        // run heads listed (in eo)
     int wsum[16];                  // workgroup tiles: kept heads per wavefront's part
 };
 
@@ -284,38 +284,25 @@ __device__ void tile_run(SegTile<MAXE>& T, const Src& S, int ra, int rb, int64_t
     // run sums at the heads, in term order within each run; a head's sum goes to
     // its own term's slot (every run reads only its own terms).  rank[t] is then
     // 1 at a kept head (a non-zero sum), 0 elsewhere.
-    if constexpr (NT > WAVE) {
-        // long tiles: the heads are listed first (in any order, each run is summed
-        // alone) and each thread sums one run, so that a wavefront waits for one
-        // run instead of one per position it visits
-        if (tid == 0) T.nh = 0;
-        __syncthreads();
-        for (int t = tid; t < total; t += NT) {
-            const uint64_t rc = T.key[t] >> IB;
-            T.rank[t] = 0;
-            if (t == 0 || (T.key[t - 1] >> IB) != rc) T.eo[atomicAdd(&T.nh, 1)] = t;
-        }
-        __syncthreads();
-        const int nh = T.nh;
-        for (int h = tid; h < nh; h += NT) {
-            const int t = T.eo[h];
-            const uint64_t rc = T.key[t] >> IB;
-            double s = 0.0;
-            for (int u = t; u < total && (T.key[u] >> IB) == rc; ++u) s += T.v[T.key[u] & IMASK];
-            T.rank[t] = s != 0.0 ? 1 : 0;
-            T.v[T.key[t] & IMASK] = s;
-        }
-    } else {
-        for (int t = tid; t < total; t += NT) {
-            uint64_t rc = T.key[t] >> IB;
-            bool head = t == 0 || (T.key[t - 1] >> IB) != rc;
-            double s = 0.0;
-            if (head) {
-                for (int u = t; u < total && (T.key[u] >> IB) == rc; ++u) s += T.v[T.key[u] & IMASK];
-            }
-            T.rank[t] = (head && s != 0.0) ? 1 : 0;
-            if (head) T.v[T.key[t] & IMASK] = s;
-        }
+    // The heads are listed first (in any order, each run is summed alone) and
+    // each thread sums one run, so that a wavefront waits for one run instead of
+    // one per position it visits.
+    if (tid == 0) T.nh = 0;
+    __syncthreads();
+    for (int t = tid; t < total; t += NT) {
+        const uint64_t rc = T.key[t] >> IB;
+        T.rank[t] = 0;
+        if (t == 0 || (T.key[t - 1] >> IB) != rc) T.eo[atomicAdd(&T.nh, 1)] = t;
+    }
+    __syncthreads();
+    const int nh = T.nh;
+    for (int h = tid; h < nh; h += NT) {
+        const int t = T.eo[h];
+        const uint64_t rc = T.key[t] >> IB;
+        double s = 0.0;
+        for (int u = t; u < total && (T.key[u] >> IB) == rc; ++u) s += T.v[T.key[u] & IMASK];
+        T.rank[t] = s != 0.0 ? 1 : 0;
+        T.v[T.key[t] & IMASK] = s;
     }
     __syncthreads();
     // exclusive ranks of the kept heads, 64 at a time: one wavefront over the
