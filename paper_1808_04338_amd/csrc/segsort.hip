@@ -351,11 +351,10 @@ __device__ void tile_run(SegTile<MAXE>& T, const Src& S, int ra, int rb, int64_t
         int s0 = (int)(T.rowoff[i] - base), s1 = (int)(T.rowoff[i + 1] - base);
         cnt[ra + i] = T.rank[s1] - T.rank[s0];
     }
-    for (int t = tid; t < total; t += NT) {
+    for (int h = tid; h < nh; h += NT) {
+        const int t = T.eo[h];
         uint64_t kt = T.key[t];
         uint64_t rc = kt >> IB;
-        bool head = t == 0 || (T.key[t - 1] >> IB) != rc;
-        if (!head) continue;
         double s = T.v[kt & IMASK];
         if (s == 0.0) continue;
         int rl = (int)(kt >> 40);
