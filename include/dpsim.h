@@ -337,12 +337,14 @@ dp_status sim_bench_kernel(dp_sim *sim, int32_t kernel, int32_t reps, double *av
 
 /* Live kernel timing inside the normal calls.  While a timer is on, every
  * launch of its kernel records a pair of HIP events on the handle's stream (up
- * to 1024 launches) and adds the launch's algorithmic bytes.  kernel: 0 FP64
+ * to 2048 launches) and adds the launch's algorithmic bytes.  kernel: 0 FP64
  * block SpMV of the decoupled matrix in GMRES; 1 block ILU(0) solve (its four
  * kernels as one launch); 2 row-wise AMG products A P and R (A P) (wavefront
  * tiles and the two workgroup tiers as one launch); 3 AMG V-cycle of the
  * pressure stage (all its levels as one launch; not timed while the
- * preconditioner replays from its graph).  on != 0 resets and
+ * preconditioner replays from its graph); 4 the two classical Gram-Schmidt
+ * passes over the Krylov basis of one GMRES iteration, with their reductions
+ * (as one launch).  on != 0 resets and
  * starts, 0 stops.  sim_kernel_time synchronises the stream and returns the
  * summed device time (ms), the number of timed launches and the summed bytes. */
 dp_status sim_kernel_timer(dp_sim *sim, int32_t kernel, int32_t on);

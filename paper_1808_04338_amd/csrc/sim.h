@@ -120,9 +120,9 @@ struct PhaseTimer {
 // enabled, every launch is bracketed by a pair of HIP events on the handle's
 // stream (up to KT_CAP launches; the events are read when the timer is queried)
 // and its algorithmic bytes are added up.
-constexpr int KT_CAP = 1024;
-constexpr int KT_N = 4;  // 0 FP64 block SpMV, 1 block ILU(0) solve, 2 row-wise AMG products,
-                         // 3 AMG V-cycle
+constexpr int KT_CAP = 2048;
+constexpr int KT_N = 5;  // 0 FP64 block SpMV, 1 block ILU(0) solve, 2 row-wise AMG products,
+                         // 3 AMG V-cycle, 4 GMRES basis passes
 struct KernelTimer {
     bool on = false;
     int used = 0;

@@ -448,12 +448,19 @@ static int gmres(dp_sim* s, double rtol, int maxit, int* iters, double* rel_res)
                 bspmv<double>(s, (const d2*)zj, (d2*)r);
                 ks.bytes(kernel_bytes(s, 0));
             }
-            // h = V^T w over v_0..v_j; for j > 0 the same pass first forms
-            // v_j = (w' - V a) / alpha in place from the previous a (at hb + 32)
-            if (j == 0) dot_multi(s, s->V, len, 1, r, len, hb);
-            else gs_finish_dot(s, s->V, len, j, hb + 32, inv_alpha, r, len, hb);
-            // w' = w - V h into slot j + 1, a = V^T w' and |w'|^2 (at hb + 32)
-            gs_update_dot_norm(s, s->V, len, j + 1, hb, r, s->V + (int64_t)(j + 1) * len, len, hb + 32);
+            {
+                // the two passes over the basis, timed as one launch; bytes: the
+                // vectors read and written (j = 0: v_0 and w twice, u written;
+                // else v_0..v_j and w, v_j written, then v_0..v_j and w, u written)
+                KtScope ks(&s->kt[4], s->stream);
+                // h = V^T w over v_0..v_j; for j > 0 the same pass first forms
+                // v_j = (w' - V a) / alpha in place from the previous a (at hb + 32)
+                if (j == 0) dot_multi(s, s->V, len, 1, r, len, hb);
+                else gs_finish_dot(s, s->V, len, j, hb + 32, inv_alpha, r, len, hb);
+                // w' = w - V h into slot j + 1, a = V^T w' and |w'|^2 (at hb + 32)
+                gs_update_dot_norm(s, s->V, len, j + 1, hb, r, s->V + (int64_t)(j + 1) * len, len, hb + 32);
+                ks.bytes(8.0 * (double)len * (j == 0 ? 5.0 : 2.0 * j + 6.0));
+            }
             DP_HIP(hipMemcpyAsync(s->hpin, hb, sizeof(double) * 64, hipMemcpyDeviceToHost, s->stream));
             DP_HIP(hipStreamSynchronize(s->stream));
             const double* hbuf = s->hpin;

@@ -225,10 +225,11 @@ class Sim:
         self._chk(self.lib.sim_amg_info(self.h, C.byref(nl), _ip(rows), _lp(nnz)))
         return nl.value, rows[:nl.value].copy(), nnz[:nl.value].copy()
 
-    TIMED_KERNELS = ("block_spmv_f64", "block_ilu0_solve", "amg_rowwise_products", "amg_vcycle")
+    TIMED_KERNELS = ("block_spmv_f64", "block_ilu0_solve", "amg_rowwise_products", "amg_vcycle",
+                     "gmres_basis_passes")
 
     def kernel_timer(self, kernel, on=True):
-        """Start (reset) or stop the live timer of kernel 0..3 (TIMED_KERNELS)."""
+        """Start (reset) or stop the live timer of kernel 0..4 (TIMED_KERNELS)."""
         self._chk(self.lib.sim_kernel_timer(self.h, int(kernel), 1 if on else 0))
 
     def kernel_time(self, kernel):
