@@ -155,6 +155,10 @@ static int red_grid(int64_t len) {
 template <int OP, int NV>
 static void red_go(dp_sim* s, int g, double* V, int64_t ld, int nv, const double* h, double sc, double* w,
                    double* wout, int64_t len, double* out) {
+    // one round of workgroups: about as many as the chip holds at once for this
+    // register bound (the larger bounds keep fewer wavefronts per SIMD)
+    constexpr int g_res = NV >= 32 ? 512 : (NV >= 16 ? 1024 : MAX_RED_BLOCKS);
+    if (g > g_res) g = g_res;
     red_kernel<OP, NV><<<g, RBLK, 0, s->stream>>>(V, ld, nv, h, sc, w, wout, len, s->red_part);
     if (red_results<OP>(nv) > 0) red_final<<<red_results<OP>(nv), RBLK, 0, s->stream>>>(s->red_part, g, out);
 }
