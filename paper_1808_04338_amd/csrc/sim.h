@@ -217,7 +217,6 @@ struct dp_sim {
     double* red_out = nullptr;    // reduction results (device)
     double red_host[256] = {};    // host copy of reduction results
     double* hpin = nullptr;        // [64] pinned host buffer of the small read-backs (GMRES coefficients, norms, sums)
-    unsigned int* red_count = nullptr;
     int red_blocks = 0;
     int64_t seg_fallbacks = 0;  // AMG products that took the global sort path
     int64_t amg_setups = 0;     // AMG setups begun over the handle's lifetime

@@ -264,7 +264,6 @@ static Layout layout(dp_sim* s, Arena& a, const HostTopo& h) {
     s->red_blocks = std::max(MAX_RED_BLOCKS_ALL, ceil_div(2 * (int64_t)n + nw, 256));
     s->red_part = a.get<double>((int64_t)s->red_blocks * 32, "reductions");
     s->red_out = a.get<double>(256, "reductions");
-    s->red_count = a.get<unsigned int>(4, "reductions");
     Layout L;
     L.persistent = a.top;
     int64_t cm = s->desc.amg_coarse_max;
@@ -973,7 +972,6 @@ dp_status sim_create(const dp_sim_desc* desc, const double* p0, const double* sw
         up(s->Ap0.rowptr, h.ap_rowptr.data(), sizeof(int) * h.ap_rowptr.size());
         up(s->Ap0.col, h.ap_col.data(), sizeof(int) * h.ap_col.size());
         up(s->ap_src, h.ap_src.data(), sizeof(int) * h.ap_src.size());
-        DP_HIP(hipMemsetAsync(s->red_count, 0, sizeof(unsigned int) * 4, st));
         // fields: staged in the setup scratch region (free until the first setup)
         Arena& sc = s->scr;
         sc.top = 0;
