@@ -897,7 +897,7 @@ __global__ void cast_vals(const double* __restrict__ a, int64_t n, T* b) {
 // last block ends at nnz <= nb * chunk: every block holds at most CSRS_CAP
 // entries.  desc[k] = (first row, its entry offset); desc[nb] = (n, nnz).  Each
 // k in [1, nb) has exactly one row r with rowptr[r-1] < k * chunk <= rowptr[r].
-constexpr int CSRS_NT = 256, CSRS_K = 4, CSRS_CAP = CSRS_NT * CSRS_K;
+constexpr int CSRS_NT = 512, CSRS_K = 4, CSRS_CAP = CSRS_NT * CSRS_K;
 
 __global__ void csrs_desc(const int* __restrict__ rowptr, int n, int64_t chunk, int nb, int2* desc) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
