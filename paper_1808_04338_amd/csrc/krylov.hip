@@ -121,19 +121,20 @@ __global__ void __launch_bounds__(RBLK) red_kernel(double* V, int64_t ld, int nv
         double b = 0.0;
 #pragma unroll
         for (int q = 0; q < RBLK / WAVE; ++q) b += sh[threadIdx.x][q];
-        part[(int64_t)blockIdx.x * KMAX + threadIdx.x] = b;
+        part[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = b;
     }
 }
 
-// out[k] = sum over the nblk block partials of result k: one workgroup per
-// result; thread t adds blocks t, t + RBLK, ... in order, then a fixed
-// wavefront butterfly and the wavefronts' sums in order.
+// out[k] = sum over the nblk block partials of result k (stored result-major,
+// part[k nblk + b], so a workgroup reads its result's partials contiguously):
+// one workgroup per result; thread t adds blocks t, t + RBLK, ... in order,
+// then a fixed wavefront butterfly and the wavefronts' sums in order.
 __global__ void __launch_bounds__(RBLK) red_final(const double* __restrict__ part, int nblk, double* out) {
     __shared__ double sh[RBLK / WAVE];
     const int k = blockIdx.x;
     const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
     double acc = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += RBLK) acc += part[(int64_t)b * KMAX + k];
+    for (int b = threadIdx.x; b < nblk; b += RBLK) acc += part[(int64_t)k * nblk + b];
     double v = wave_sum(acc);
     if (lane == 0) sh[wv] = v;
     __syncthreads();
